@@ -1,0 +1,154 @@
+/*
+ * fh.h -- C ABI of the MI355X (gfx950) generalized FrequencyHough library.
+ *
+ * Method (Miller et al., "A method to search for long duration gravitational
+ * wave transients from isolated neutron stars using the generalized
+ * FrequencyHough"):
+ *   Sec. II, Eqs. diff_powlaws/powlaws: the signal model fdot = -k f^n.
+ *   Sec. IV, Eq. transform: x = f^(1-n) turns it into x = x0 + (n-1) k (t - t0),
+ *     so each peakmap peak (t, f) is a line in the (x0, k) plane and the Hough
+ *     map is the histogram of those lines.
+ *   Sec. VI.B: the k grid (given here as an explicit ascending array).
+ *   Sec. VI.C: the uniform x0 grid with step (n-1) df / f_max^n from f_max^(1-n).
+ *   Sec. IV (candidate selection, Eq. for CR): squares, critical ratio.
+ *
+ * Conventions for every entry point:
+ *   - Return FH_OK or a negative fh_status; arguments are validated before any
+ *     work is enqueued, so an error return means nothing was written.
+ *   - No exceptions, aborts or exits cross this boundary.
+ *   - Device pointers are HIP device allocations on the current device,
+ *     owned by the caller.  Host pointers are read during the call only.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Calls that take a stream are asynchronous on it unless stated.
+ *   - A plan may be used from one stream at a time (it owns scratch).
+ *
+ * The peak bin b of FFT i stands for the frequency bin [f_min + b df,
+ * f_min + (b+1) df), df = 1/tfft.  Its x-image is shifted, at row r and time
+ * T_i, to x0-columns floor(u_lo) .. floor(u_hi), clipped to [0, n_x0), with
+ *   u = fma(-C_r, T_i, A_b)   (binary64, one rounding)
+ *   A_b = (pow(f_min + b*df, 1-n) - x0_min) * (1/dx0),  C_r = ((n-1)*k_r) * (1/dx0),
+ *   T_i = t[i] if given, else (i + 0.5) * tfft  (FFT mid-time, t0 = start),
+ * u_lo using the bin's upper edge b+1 and u_hi its lower edge b.  Every
+ * operation is one IEEE binary64 operation rounded to nearest, no
+ * contraction, on the host (tables) and on the device (u); counts are exact.
+ */
+#ifndef FH_H
+#define FH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FH_OK = 0,
+  FH_EINVAL = -1,   /* invalid argument (description, sizes, pointers) */
+  FH_ENOMEM = -2,   /* device or host allocation failed */
+  FH_EDEVICE = -3,  /* a HIP call failed (launch, copy, graph) */
+  FH_ERANGE = -4    /* sizes exceed the library's limits (e.g. n_k*n_x0 >= 2^31) */
+} fh_status;
+
+typedef struct fh_plan_s* fh_plan_t;
+
+/* One Hough map (Sec. IV/VI).  All arrays are HOST memory, read by fh_plan. */
+typedef struct {
+  double n;          /* braking index; finite, n > 1 (Sec. II) */
+  double tfft;       /* FFT length in s; df = 1/tfft (Sec. VI.A) */
+  double f_min;      /* band of the peakmap in Hz; 0 < f_min < f_max and */
+  double f_max;      /*   (f_max - f_min)*tfft integral within 1e-9 */
+  int32_t n_fft;     /* number of FFTs (time rows of the peakmap), >= 1 */
+  const double* t;   /* [n_fft] t_i - t0 in s, ascending, finite; NULL = (i+0.5)*tfft */
+  int32_t n_k;       /* rows of the map, >= 1 */
+  const double* k;   /* [n_k] ascending, finite, k >= 0 (Sec. VI.B) */
+  double x0_min;     /* x0 of column 0; used only if dx0 != 0 */
+  double dx0;        /* column width; 0 = defaults x0_min = f_max^(1-n), */
+                     /*   dx0 = ((n-1)/tfft) f_max^-n (Sec. VI.C); else > 0 */
+  int32_t n_x0;      /* columns; 0 = ceil(f_max((f_max/f_min)^(n-1)-1)/((n-1)df) - 1e-9) */
+} fh_map_desc;
+
+/* Peakmap as a CSR by FFT, DEVICE memory: FFT i owns bin[row_ptr[i] ..
+ * row_ptr[i+1]), frequency-bin indices strictly ascending within an FFT.
+ * row_ptr has n_fft+1 entries, row_ptr[0] = 0, non-decreasing, row_ptr[n_fft]
+ * = n_peaks (not checked on the host: it lives on the device).  Bins outside
+ * [0, n_f) are skipped and counted in the plan's device error word; a
+ * non-ascending FFT is counted there too and leaves that FFT's counts in the
+ * windowed mode unspecified (never out-of-bounds memory access). */
+typedef struct {
+  const int32_t* row_ptr;
+  const int32_t* bin;
+  int64_t n_peaks;
+} fh_peaks;
+
+/* Tile shape of the Hough kernel; zeros = automatic.  mode 1 = every tile
+ * reads whole FFTs (small maps), mode 2 = tiles read only the peaks whose
+ * image can reach their columns (wide maps). */
+typedef struct {
+  int32_t rows;     /* k rows per tile */
+  int32_t cols;     /* x0 columns per tile */
+  int32_t threads;  /* work-group size: 256 or 512 */
+  int32_t mode;     /* 0 auto, 1 whole-FFT, 2 windowed */
+} fh_tile_cfg;
+
+typedef struct {
+  int32_t n_f, n_x0, n_k, n_fft;
+  double x0_min, dx0;
+  fh_tile_cfg tile;      /* the resolved tile shape */
+  int64_t n_tiles;
+  int64_t workspace_bytes;
+} fh_plan_info;
+
+/* Validate a map description, compute the FP64 tables on the host and upload
+ * them, choose the tile shape (cfg NULL or zeros = automatic) and allocate the
+ * plan's device workspace on the current device.  Synchronous.
+ * Errors: FH_EINVAL (bad description), FH_ERANGE (n_k*n_x0 >= 2^31 or
+ * n_f > 2^24), FH_ENOMEM, FH_EDEVICE.  *out is set only on FH_OK. */
+fh_status fh_plan(const fh_map_desc* desc, const fh_tile_cfg* cfg, fh_plan_t* out);
+fh_status fh_plan_get_info(fh_plan_t plan, fh_plan_info* out);
+/* Host copies of the plan's tables: A [n_f+1], C [n_k], T [n_fft]; any may be NULL. */
+fh_status fh_plan_tables(fh_plan_t plan, double* A, double* C, double* T);
+void fh_plan_destroy(fh_plan_t plan);
+
+/* The generalized FrequencyHough of one peakmap (Sec. IV): writes every cell
+ * of map (DEVICE int32 [n_k][n_x0], row-major, x0 ascending = frequency
+ * descending), so the caller need not clear it.  Counts are exact.
+ * Errors (nothing enqueued): FH_EINVAL for NULL pointers or n_peaks < 0 or
+ * n_peaks >= 2^31; FH_EDEVICE if a launch fails. */
+fh_status fh_hough(fh_plan_t plan, const fh_peaks* peaks, int32_t* map, void* stream);
+
+/* Number of bad peaks (bin outside [0,n_f), or not ascending) seen by the last
+ * fh_hough / batch launch of this plan.  Synchronises `stream`. */
+fh_status fh_device_errors(fh_plan_t plan, void* stream, uint64_t* out);
+
+/* ----------------------------------------------------------- batching --
+ * Many maps of uneven size in one persistent launch: every tile of every map
+ * goes into one work queue, longest (estimated) first, claimed by a grid of
+ * resident work-groups through an atomic counter; the launch is captured in a
+ * hipGraph once and replayed.  Each map i uses plans[i] (its grid and tile
+ * shape), peaks[i] and maps[i]; several maps may share one peakmap. */
+typedef struct fh_batch_s* fh_batch_t;
+
+/* Build the work queue and the graph.  Host arrays of length m (>= 1) are read
+ * during the call; the plans must outlive the batch; the peak and map device
+ * buffers must stay valid while the batch is launched.  Synchronous. */
+fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh_peaks* peaks, int32_t* const* maps,
+                          fh_batch_t* out);
+/* Enqueue one replay of the batch on `stream`. */
+fh_status fh_batch_launch(fh_batch_t batch, void* stream);
+/* Same work without the graph or the queue: one fh_hough launch per map. */
+fh_status fh_batch_launch_plain(fh_batch_t batch, void* stream);
+void fh_batch_destroy(fh_batch_t batch);
+
+/* One-shot convenience: create, launch on `stream`, synchronise, destroy. */
+fh_status fh_hough_batched(int32_t m, const fh_plan_t* plans, const fh_peaks* peaks, int32_t* const* maps,
+                           void* stream);
+
+const char* fh_status_str(fh_status s);
+/* Library version string, and the gfx architecture it was built for. */
+const char* fh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FH_H */
