@@ -84,10 +84,12 @@ typedef struct {
  * reads whole FFTs (small maps), mode 2 = tiles read only the peaks whose
  * image can reach their columns (wide maps). */
 typedef struct {
-  int32_t rows;     /* k rows per tile */
+  int32_t rows;     /* k rows per tile, 1..64 */
   int32_t cols;     /* x0 columns per tile */
   int32_t threads;  /* work-group size: 256 or 512 */
   int32_t mode;     /* 0 auto, 1 whole-FFT, 2 windowed */
+  int32_t tsplit;   /* the FFTs are split into this many ranges, one tile each; */
+                    /*   > 1: tiles add into the map with atomics after a clear */
 } fh_tile_cfg;
 
 typedef struct {

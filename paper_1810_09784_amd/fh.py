@@ -1,0 +1,245 @@
+"""Thin ctypes binding of libfh.so (the C ABI in include/fh.h).
+
+Argument marshalling only: torch tensors supply device memory and the current
+HIP stream; every step of the computation runs in the library's kernels.  The
+library must have been built (paper_1810_09784_amd/build.py); there is no
+fallback of any kind."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfh.so")
+
+FH_OK, FH_EINVAL, FH_ENOMEM, FH_EDEVICE, FH_ERANGE = 0, -1, -2, -3, -4
+
+
+class FHError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {status_str(status)} ({status})")
+        self.status = status
+
+
+class MapDesc(C.Structure):
+    _fields_ = [("n", C.c_double), ("tfft", C.c_double), ("f_min", C.c_double), ("f_max", C.c_double),
+                ("n_fft", C.c_int32), ("t", C.POINTER(C.c_double)), ("n_k", C.c_int32),
+                ("k", C.POINTER(C.c_double)), ("x0_min", C.c_double), ("dx0", C.c_double), ("n_x0", C.c_int32)]
+
+
+class Peaks(C.Structure):
+    _fields_ = [("row_ptr", C.c_void_p), ("bin", C.c_void_p), ("n_peaks", C.c_int64)]
+
+
+class TileCfg(C.Structure):
+    _fields_ = [("rows", C.c_int32), ("cols", C.c_int32), ("threads", C.c_int32), ("mode", C.c_int32),
+                ("tsplit", C.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class PlanInfo(C.Structure):
+    _fields_ = [("n_f", C.c_int32), ("n_x0", C.c_int32), ("n_k", C.c_int32), ("n_fft", C.c_int32),
+                ("x0_min", C.c_double), ("dx0", C.c_double), ("tile", TileCfg), ("n_tiles", C.c_int64),
+                ("workspace_bytes", C.c_int64)]
+
+
+_lib = None
+
+# name -> (restype, argtypes); every symbol include/fh.h declares
+SIGNATURES = {
+    "fh_plan": (C.c_int, [C.POINTER(MapDesc), C.POINTER(TileCfg), C.POINTER(C.c_void_p)]),
+    "fh_plan_get_info": (C.c_int, [C.c_void_p, C.POINTER(PlanInfo)]),
+    "fh_plan_tables": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fh_plan_destroy": (None, [C.c_void_p]),
+    "fh_hough": (C.c_int, [C.c_void_p, C.POINTER(Peaks), C.c_void_p, C.c_void_p]),
+    "fh_device_errors": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)]),
+    "fh_batch_create": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(Peaks), C.POINTER(C.c_void_p),
+                                  C.POINTER(C.c_void_p)]),
+    "fh_batch_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "fh_batch_launch_plain": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "fh_batch_destroy": (None, [C.c_void_p]),
+    "fh_hough_batched": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(Peaks), C.POINTER(C.c_void_p),
+                                   C.c_void_p]),
+    "fh_status_str": (C.c_char_p, [C.c_int]),
+    "fh_version": (C.c_char_p, []),
+}
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_1810_09784_amd/build.py "
+                               "(or __graft_entry__.build())")
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()  # one HIP runtime (torch's) initialised before the library's first call
+            torch.zeros(1, device="cuda")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_str(s: int) -> str:
+    return lib().fh_status_str(int(s)).decode()
+
+
+def _check(st: int, what: str):
+    if st != FH_OK:
+        raise FHError(st, what)
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+class Plan:
+    """fh_plan: a validated map description with its device tables."""
+
+    def __init__(self, n: float, tfft: float, f_min: float, f_max: float, n_fft: int, k: Sequence[float],
+                 t: Optional[Sequence[float]] = None, x0_min: float = 0.0, dx0: float = 0.0, n_x0: int = 0,
+                 tile: Optional[dict] = None):
+        self._k = np.ascontiguousarray(k, dtype=np.float64)
+        self._t = None if t is None else np.ascontiguousarray(t, dtype=np.float64)
+        dp = C.POINTER(C.c_double)
+        self.desc = MapDesc(float(n), float(tfft), float(f_min), float(f_max), int(n_fft),
+                            dp() if self._t is None else self._t.ctypes.data_as(dp), int(self._k.shape[0]),
+                            self._k.ctypes.data_as(dp), float(x0_min), float(dx0), int(n_x0))
+        cfg = None
+        if tile:
+            cfg = TileCfg(int(tile.get("rows", 0)), int(tile.get("cols", 0)), int(tile.get("threads", 0)),
+                          int(tile.get("mode", 0)), int(tile.get("tsplit", 1)))
+        h = C.c_void_p()
+        _check(lib().fh_plan(C.byref(self.desc), C.byref(cfg) if cfg else None, C.byref(h)), "fh_plan")
+        self.handle = h
+        info = PlanInfo()
+        _check(lib().fh_plan_get_info(h, C.byref(info)), "fh_plan_get_info")
+        self.info = info
+
+    @classmethod
+    def from_spec(cls, spec, **kw):
+        return cls(spec.n, spec.tfft, spec.f_min, spec.f_max, spec.n_fft, spec.k, **kw)
+
+    @property
+    def n_k(self):
+        return int(self.info.n_k)
+
+    @property
+    def n_x0(self):
+        return int(self.info.n_x0)
+
+    @property
+    def n_f(self):
+        return int(self.info.n_f)
+
+    @property
+    def tile(self):
+        return self.info.tile.as_dict()
+
+    def tables(self):
+        A = np.empty(self.n_f + 1)
+        Cr = np.empty(self.n_k)
+        T = np.empty(int(self.info.n_fft))
+        _check(lib().fh_plan_tables(self.handle, A.ctypes.data, Cr.ctypes.data, T.ctypes.data), "fh_plan_tables")
+        return A, Cr, T
+
+    def destroy(self):
+        if self.handle:
+            lib().fh_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def fh_plan(*args, **kw) -> Plan:
+    return Plan(*args, **kw)
+
+
+def peaks_struct(row_ptr, bin_) -> Peaks:
+    """row_ptr / bin: int32 CUDA tensors (CSR by FFT)."""
+    import torch
+    assert row_ptr.is_cuda and bin_.is_cuda and row_ptr.dtype == torch.int32 and bin_.dtype == torch.int32
+    assert row_ptr.is_contiguous() and bin_.is_contiguous()
+    return Peaks(_ptr(row_ptr), _ptr(bin_) if bin_.numel() else 0, int(bin_.numel()))
+
+
+def fh_hough(plan: Plan, row_ptr, bin_, out=None, stream=None):
+    """Hough map of one peakmap; returns (or fills) an int32 [n_k, n_x0] CUDA tensor."""
+    import torch
+    if out is None:
+        out = torch.empty((plan.n_k, plan.n_x0), dtype=torch.int32, device=row_ptr.device)
+    assert out.dtype == torch.int32 and out.is_contiguous() and tuple(out.shape) == (plan.n_k, plan.n_x0)
+    if row_ptr.numel() != int(plan.info.n_fft) + 1:
+        raise ValueError("row_ptr must have n_fft + 1 entries")
+    pk = peaks_struct(row_ptr, bin_)
+    _check(lib().fh_hough(plan.handle, C.byref(pk), C.c_void_p(_ptr(out)), _stream(stream)), "fh_hough")
+    return out
+
+
+def fh_device_errors(plan: Plan, stream=None) -> int:
+    v = C.c_uint64()
+    _check(lib().fh_device_errors(plan.handle, _stream(stream), C.byref(v)), "fh_device_errors")
+    return int(v.value)
+
+
+class Batch:
+    """fh_batch_*: many maps in one persistent, graph-captured launch."""
+
+    def __init__(self, plans: List[Plan], peaks: List[tuple], maps: List):
+        m = len(plans)
+        for p, (rp, _), x in zip(plans, peaks, maps):
+            if rp.numel() != int(p.info.n_fft) + 1 or tuple(x.shape) != (p.n_k, p.n_x0):
+                raise ValueError("peaks / map do not match the plan")
+        self._keep = (plans, peaks, maps)
+        self._plans = (C.c_void_p * m)(*[p.handle.value for p in plans])
+        self._peaks = (Peaks * m)(*[peaks_struct(rp, b) for rp, b in peaks])
+        self._maps = (C.c_void_p * m)(*[_ptr(x) for x in maps])
+        h = C.c_void_p()
+        _check(lib().fh_batch_create(m, self._plans, self._peaks, self._maps, C.byref(h)), "fh_batch_create")
+        self.handle = h
+
+    def launch(self, stream=None):
+        _check(lib().fh_batch_launch(self.handle, _stream(stream)), "fh_batch_launch")
+
+    def launch_plain(self, stream=None):
+        _check(lib().fh_batch_launch_plain(self.handle, _stream(stream)), "fh_batch_launch_plain")
+
+    def destroy(self):
+        if self.handle:
+            lib().fh_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def fh_hough_batched(plans: List[Plan], peaks: List[tuple], maps: List, stream=None):
+    m = len(plans)
+    P = (C.c_void_p * m)(*[p.handle.value for p in plans])
+    K = (Peaks * m)(*[peaks_struct(rp, b) for rp, b in peaks])
+    M = (C.c_void_p * m)(*[_ptr(x) for x in maps])
+    _check(lib().fh_hough_batched(m, P, K, M, _stream(stream)), "fh_hough_batched")
+    return maps

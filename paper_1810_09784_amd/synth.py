@@ -195,14 +195,18 @@ def cfg_single_small(noiseless: bool = False, seed: int = 1) -> MapSpec:
 
 
 def _draw_injections(rng, n_inj, n, f_lo, f_hi, k_max, amp_lo, amp_hi, tau_lo=1e3, tau_hi=1e5):
+    """f0 uniform in the band, tau log-uniform in [tau_lo, tau_hi], restricted
+    to k <= k_max (the searched k range): where the whole tau range would give
+    k > k_max the range is moved up to start at the smallest admissible tau."""
     out = []
-    while len(out) < n_inj:
+    for _ in range(n_inj):
         f0 = rng.uniform(f_lo, f_hi)
-        tau = 10.0 ** rng.uniform(math.log10(tau_lo), math.log10(tau_hi))
+        tau_min = 1.0 / (k_max * (n - 1.0) * f0 ** (n - 1.0)) * (1.0 + 1e-9)
+        lo = max(tau_lo, tau_min)
+        hi = max(tau_hi, 10.0 * lo)
+        tau = 10.0 ** rng.uniform(math.log10(lo), math.log10(hi))
         amp = rng.uniform(amp_lo, amp_hi)
-        inj = Injection(f0=f0, tau=tau, n=n, amp=amp)
-        if inj.k <= k_max:
-            out.append(inj)
+        out.append(Injection(f0=f0, tau=tau, n=n, amp=amp))
     return out
 
 
