@@ -118,6 +118,12 @@ void fh_plan_destroy(fh_plan_t plan);
  * n_peaks >= 2^31; FH_EDEVICE if a launch fails. */
 fh_status fh_hough(fh_plan_t plan, const fh_peaks* peaks, int32_t* map, void* stream);
 
+/* Profiling hook: when start/stop (hipEvent_t, passed as void*) are set,
+ * every later fh_hough of this plan records `start` on its stream right before
+ * the Hough tile kernel and `stop` right after it, so the kernel alone can be
+ * timed on the stream it runs on.  NULL, NULL clears the hook. */
+fh_status fh_plan_set_events(fh_plan_t plan, void* start, void* stop);
+
 /* Number of bad peaks (bin outside [0,n_f), or not ascending) seen by the last
  * fh_hough / batch launch of this plan.  Synchronises `stream`. */
 fh_status fh_device_errors(fh_plan_t plan, void* stream, uint64_t* out);

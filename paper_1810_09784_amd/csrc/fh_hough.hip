@@ -4,12 +4,13 @@
 // lines through each cell).
 //
 // Work decomposition.  The map is cut into tiles of `rows` k-rows x `cols`
-// x0-columns (optionally also into `tsplit` ranges of FFTs).  One work-group
-// owns one tile: it keeps a differential copy of the tile in LDS (int32,
+// x0-columns; a tile whose estimated work is large is further split into
+// FFT ranges (work units).  A work-group runs one unit at a time from a
+// queue ordered longest first: it keeps a differential copy of the tile in LDS (int32,
 // one spare column per row), adds +1 at the first and -1 after the last
 // column of every (peak, row) interval that meets the tile (LDS atomics),
 // then prefix-sums every row with wavefront DPP scans and stores it with
-// coalesced dword writes (or atomically adds it when time is split).
+// coalesced dword writes (or atomically adds it when the tile is split).
 //
 // Index arithmetic (identical on the host tables and here): for bin j, row r,
 // FFT i:  u = fma(-C_r, T_i, A_j);  the interval is [floor(u_lo), floor(u_hi)]
@@ -122,34 +123,58 @@ __device__ void fft_range(const MapArgs& M, double C, int c0, int c1, int i_lo, 
   *ib = b;
 }
 
+// Inclusive max-scan over the wavefront (same DPP pattern as the sum).
+__device__ __forceinline__ int wave_incl_max(int x) {
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false));
+  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false));
+  return x;
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Per-wave LDS scratch of the whole-FFT mode: one block of 64 FFTs.
+struct WaveScratch {
+  double T[kWave];     // time of each FFT of the block
+  int rb[kWave];       // rows that can reach the tile at that FFT
+  int rp[kWave + 4];   // CSR offsets of the block (65 used)
+};
+static_assert(sizeof(WaveScratch) == 1040, "per-wave LDS scratch size is part of the LDS budget");
+
+// One unit: tile `tile` of map M over FFTs [i_lo, i_hi); `atomic` when the
+// tile is split over several units (the map region was cleared beforehand).
 template <int THREADS, bool ALDS>
-__device__ void tile_body(const MapArgs& M, int tile, char* smem) {
+__device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool atomic, char* smem) {
   constexpr int NW = THREADS / kWave;
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = uniform(tid >> 6);
 
-  const int nxy = M.tiles_x * M.tiles_y;
-  const int ts = tile / nxy;
-  const int rem = tile - ts * nxy;
-  const int rt = rem / M.tiles_x;
-  const int ct = rem - rt * M.tiles_x;
+  const int rt = tile / M.tiles_x;
+  const int ct = tile - rt * M.tiles_x;
   const int r0 = rt * M.rows;
   const int nrows = min(M.rows, M.n_k - r0);
   const int c0 = ct * M.cols;
   const int c1 = min(c0 + M.cols, M.n_x0);
   const int W = c1 - c0;
-  const int i_lo = (int)((long long)M.n_fft * ts / M.tsplit);
-  const int i_hi = (int)((long long)M.n_fft * (ts + 1) / M.tsplit);
   const int pitch = M.pitch;
 
+  // LDS: [A (n_f+1) doubles][C rows doubles][wave scratch x NW][ia rows][ib rows][wtot 16][flags 4][D rows*pitch]
   double* A_s = reinterpret_cast<double*>(smem);
   double* C_s = A_s + (ALDS ? (M.n_f + 1) : 0);
-  int* ia_s = reinterpret_cast<int*>(C_s + M.rows);
+  WaveScratch* wsc = reinterpret_cast<WaveScratch*>(C_s + M.rows);
+  int* ia_s = reinterpret_cast<int*>(wsc + NW);
   int* ib_s = ia_s + M.rows;
-  int* wtot = ib_s + M.rows;           // per-wave partial sums (16 ints)
-  int* span = wtot + 16;               // FFT union range (2 ints)
-  int* D = span + 2 + ((4 - ((M.rows * 2 + 18) & 3)) & 3);
+  int* wtot = ib_s + M.rows;  // per-wave partial sums (16 ints)
+  int* flags = wtot + 16;     // [0]: ib non-increasing over the rows, [1] [2]: union FFT range
+  int* D = flags + 4;
   const double* A = ALDS ? A_s : M.A;
 
   if (ALDS)
@@ -164,63 +189,84 @@ __device__ void tile_body(const MapArgs& M, int tile, char* smem) {
     ib_s[tid] = b;
   }
   __syncthreads();
-
-  const bool count_bad = (rt == 0 && ct == 0);  // each (FFT, peak) counted by one tile
-
-  if (M.mode == kModeWhole) {
-    int i_start = i_hi, i_end = i_lo;
+  if (tid == 0) {
+    int mono = 1, lo = i_hi, hi = i_lo;
     for (int r = 0; r < nrows; ++r) {
+      if (r > 0) mono &= ib_s[r] <= ib_s[r - 1];
       if (ia_s[r] < ib_s[r]) {
-        i_start = min(i_start, ia_s[r]);
-        i_end = max(i_end, ib_s[r]);
+        lo = min(lo, ia_s[r]);
+        hi = max(hi, ib_s[r]);
       }
     }
-    if (count_bad) {
-      i_start = i_lo;
-      i_end = i_hi;
-    }
-    i_start = uniform(i_start);
-    i_end = uniform(i_end);
-    for (int i = i_start + wave; i < i_end; i += NW) {
-      const bool act = lane < nrows && ia_s[lane] <= i && i < ib_s[lane];
-      const unsigned long long amask = __ballot(act);
-      if (!amask && !count_bad) continue;
-      const int pa = uniform(min(max(M.row_ptr[i], 0), M.n_peaks));
-      const int pb = uniform(min(max(M.row_ptr[i + 1], pa), M.n_peaks));
-      const int m = pb - pa;
-      if (m <= 0) continue;
-      const double T = M.T[i];
-      const int lsh = m >= 64 ? 6 : (m <= 1 ? 0 : 32 - __builtin_clz((unsigned)(m - 1)));  // ceil(log2 m)
-      const int mp = 1 << lsh;
-      const int q = lane >> lsh;      // row slot
-      const int slot = lane & (mp - 1);
-      const int ra = amask ? __builtin_ctzll(amask) : 0;
-      const int rb = amask ? 64 - __builtin_clzll(amask) : 0;
-      const int G = kWave >> lsh;
-      for (int pc = pa; pc < pb; pc += kWave) {
-        const int p = pc + slot;
-        const bool pv = p < pb;
-        const int j = M.bin[pv ? p : pa];  // in bounds: pa < pb <= n_peaks
+    flags[0] = mono;
+    flags[1] = lo;
+    flags[2] = hi;
+  }
+  __syncthreads();
+
+  if (M.mode == kModeWhole) {
+    // Waves take blocks of 64 FFTs; lanes take the blocks' peaks 64 at a time
+    // (coalesced) and loop over the tile rows that can reach the tile.
+    const bool count_bad = (rt == 0 && ct == 0);  // each peak counted by one tile
+    const int mono = flags[0];
+    const int i_start = uniform(count_bad ? i_lo : flags[1]);
+    const int i_end = uniform(count_bad ? i_hi : max(flags[2], flags[1]));
+    WaveScratch& S = wsc[wave];
+    for (int f0 = i_start + wave * kWave; f0 < i_end; f0 += NW * kWave) {
+      const int nb = min(kWave, i_end - f0);
+      const int fi = f0 + min(lane, nb - 1);
+      const int rp_l = min(max(M.row_ptr[f0 + min(lane, nb)], 0), M.n_peaks);
+      const int rp_e = uniform(min(max(M.row_ptr[f0 + nb], 0), M.n_peaks));
+      int rb = nrows;
+      if (mono) {
+        int u = 0, w = nrows;  // first r with ib_r <= fi
+        while (u < w) {
+          const int mid = (u + w) >> 1;
+          if (ib_s[mid] > fi) u = mid + 1; else w = mid;
+        }
+        rb = u;
+      }
+      wave_sync_lds();
+      S.rp[lane] = rp_l;
+      if (lane == 0) S.rp[kWave] = rp_e;
+      S.T[lane] = M.T[fi];
+      S.rb[lane] = lane < nb ? rb : 0;
+      wave_sync_lds();
+      const int Pa = uniform(S.rp[0]);
+      const int Pb = max(rp_e, Pa);
+      for (int pc = Pa; pc < Pb; pc += kWave) {
+        const int p = pc + lane;
+        const bool pv = p < Pb;
+        const int pcl = pv ? p : Pa;
+        // block FFT of the peak: last k < nb with rp[k] <= p
+        int u = 0, w = nb - 1;
+        while (u < w) {
+          const int mid = (u + w + 1) >> 1;
+          if (S.rp[mid] <= pcl) u = mid; else w = mid - 1;
+        }
+        const double T = S.T[u];
+        const int j = M.bin[pcl];
         const bool jv = pv && (unsigned)j < (unsigned)M.n_f;
-        if (count_bad && q == 0 && pv && !jv) atomicAdd(M.err, 1ull);
+        if (count_bad && pv && !jv) atomicAdd(M.err, 1ull);
         const int jc = jv ? j : 0;
         const double a_hi = A[jc];
         const double a_lo = A[jc + 1];
-        for (int rg = ra; rg < rb; rg += G) {
-          const int rl = rg + q;
-          const bool v = jv && rl < rb;
-          const int rs = v ? rl : 0;
-          edge_update(D + rs * pitch, C_s[rs], T, a_lo, a_hi, c0, c1, v);
-        }
+        const int rbl = jv ? S.rb[u] : 0;
+        for (int r = 0; r < rbl; ++r) edge_update(D + r * pitch, C_s[r], T, a_lo, a_hi, c0, c1, true);
       }
     }
   } else {
+    // Per row: each lane owns one FFT, finds the peaks whose image can reach
+    // the tile's columns and walks them (four loads in flight per lane).
     for (int rl = 0; rl < nrows; ++rl) {
       const int ia = ia_s[rl], ib = ib_s[rl];
       const double C = C_s[rl];
       int* Drow = D + rl * pitch;
-      for (int i = ia + wave; i < ib; i += NW) {
-        const double T = M.T[i];
+      for (int qb = ia + wave * kWave; qb < ib; qb += NW * kWave) {
+        const int i = qb + lane;
+        const bool iv = i < ib;
+        const int ic = iv ? i : ia;
+        const double T = M.T[ic];
         const double s = C * T;
         // a superset of the bins whose image can meet [c0, c1): A_j >= c0 + s and
         // A_{j+1} < c1 + s, each widened by one column against rounding
@@ -234,20 +280,23 @@ __device__ void tile_body(const MapArgs& M, int tile, char* smem) {
         else if (y1 >= (double)(M.n_J - 1)) ja = M.J[M.n_J - 1];
         else ja = M.J[(int)__builtin_ceil(y1)];
         ja = max(ja, 0);
-        if (jb < ja) continue;
-        const int base = min(max(M.row_ptr[i], 0), M.n_peaks);
-        const int end = min(max(M.row_ptr[i + 1], base), M.n_peaks);
-        const int pa = uniform(min(base + peak_rank(M, i, ja), end));
-        const int pb = uniform(min(base + peak_rank(M, i, jb + 1), end));
-        for (int pc = pa; pc < pb; pc += kWave) {
-          const int p = pc + lane;
-          const bool pv = p < pb;
-          const int j = M.bin[pv ? p : pa];  // in bounds: pa < pb <= n_peaks
-          const bool jv = pv && (unsigned)j < (unsigned)M.n_f;
-          const int jc = jv ? j : 0;
-          const double a_hi = A[jc];
-          const double a_lo = A[jc + 1];
-          edge_update(Drow, C, T, a_lo, a_hi, c0, c1, jv);
+        const int base = min(max(M.row_ptr[ic], 0), M.n_peaks);
+        const int end = min(max(M.row_ptr[ic + 1], base), M.n_peaks);
+        int pa = 0, pe = 0;
+        if (iv && jb >= ja) {
+          pa = min(base + peak_rank(M, ic, ja), end);
+          pe = max(min(base + peak_rank(M, ic, jb + 1), end), pa);
+        }
+        for (int p = pa; p < pe; p += 4) {
+          const int q1 = min(p + 1, pe - 1), q2 = min(p + 2, pe - 1), q3 = min(p + 3, pe - 1);
+          const int j0 = M.bin[p], j1 = M.bin[q1], j2 = M.bin[q2], j3 = M.bin[q3];
+          const int jj[4] = {j0, j1, j2, j3};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const bool jv = (p + u < pe) && (unsigned)jj[u] < (unsigned)M.n_f;
+            const int jc = jv ? jj[u] : 0;
+            edge_update(Drow, C, T, A[jc + 1], A[jc], c0, c1, jv);
+          }
         }
       }
     }
@@ -255,7 +304,7 @@ __device__ void tile_body(const MapArgs& M, int tile, char* smem) {
   __syncthreads();
 
   // prefix sums along x0 and the store
-  const bool accumulate = M.tsplit > 1;
+  const bool accumulate = atomic;
   if (nrows >= NW) {
     for (int rl = wave; rl < nrows; rl += NW) {
       const int* Drow = D + rl * pitch;
@@ -310,17 +359,12 @@ __device__ void tile_body(const MapArgs& M, int tile, char* smem) {
   }
 }
 
+// Persistent work-queue kernel: work-groups claim units (ordered longest
+// first) through an atomic counter until the queue is empty.  maps == nullptr:
+// every unit belongs to M0.
 template <int THREADS, bool ALDS>
-__global__ void __launch_bounds__(THREADS) k_hough(MapArgs M) {
-  extern __shared__ __align__(16) char smem[];
-  tile_body<THREADS, ALDS>(M, blockIdx.x, smem);
-}
-
-// Persistent batched kernel: work-groups claim (map, tile) entries of a queue
-// (ordered longest first) until it is empty.
-template <int THREADS>
-__global__ void __launch_bounds__(THREADS) k_hough_batched(const MapArgs* __restrict__ maps,
-                                                          const int2* __restrict__ queue, int n_queue, int* head) {
+__global__ void __launch_bounds__(THREADS) k_queue(MapArgs M0, const MapArgs* __restrict__ maps,
+                                                  const Unit* __restrict__ units, int n_units, int* head) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_item;
   for (;;) {
@@ -328,11 +372,36 @@ __global__ void __launch_bounds__(THREADS) k_hough_batched(const MapArgs* __rest
     __syncthreads();
     const int q = s_item;
     __syncthreads();
-    if (q >= n_queue) break;
-    const int2 e = queue[q];
-    const MapArgs M = maps[e.x];
-    tile_body<THREADS, true>(M, e.y, smem);
+    if (q >= n_units) break;
+    const Unit u = units[q];
+    const int mi = u.x & ~kUnitAtomic;
+    if (maps) {
+      const MapArgs M = maps[mi];
+      tile_body<THREADS, ALDS>(M, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, smem);
+    } else {
+      tile_body<THREADS, ALDS>(M0, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, smem);
+    }
     __syncthreads();
+  }
+}
+
+// Before a launch: queue head and error words to zero, split tiles cleared.
+__global__ void k_prologue(MapArgs M0, const MapArgs* __restrict__ maps, int n_maps, const int4* __restrict__ clears,
+                           int n_clears, int* head) {
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0) *head = 0;
+    for (int m = threadIdx.x; m < n_maps; m += blockDim.x) *(maps ? maps[m].err : M0.err) = 0;
+  }
+  for (int c = blockIdx.x; c < n_clears; c += gridDim.x) {
+    const int4 e = clears[c];
+    const MapArgs& M = maps ? maps[e.x] : M0;
+    const int rt = e.y / M.tiles_x, ct = e.y % M.tiles_x;
+    const int r0 = rt * M.rows, nrows = min(M.rows, M.n_k - r0);
+    const int c0 = ct * M.cols, W = min(M.cols, M.n_x0 - c0);
+    for (int x = threadIdx.x; x < nrows * W; x += blockDim.x) {
+      const int r = x / W, col = x - r * W;
+      M.map[(size_t)(r0 + r) * M.n_x0 + c0 + col] = 0;
+    }
   }
 }
 
@@ -360,7 +429,7 @@ __device__ void prepare_one(const MapArgs& M, long long t) {
   }
   if (w == 0) bad += (unsigned long long)(a - lo);
   if (w == M.n_words - 1) bad += (unsigned long long)(hi - q);
-  const_cast<uint2*>(M.rank)[(size_t)i * M.n_words + w] = make_uint2((unsigned)(a - lo), mask);
+  M.rank[(size_t)i * M.n_words + w] = make_uint2((unsigned)(a - lo), mask);
   if (bad) atomicAdd(M.err, bad);
 }
 
@@ -380,47 +449,41 @@ __global__ void k_prepare_batch(const MapArgs* __restrict__ maps, int m) {
   }
 }
 
-// Error words of every map, and the maps of time-split plans, cleared.
-__global__ void k_clear_batch(const MapArgs* __restrict__ maps, int m) {
-  const long long st = (long long)gridDim.x * blockDim.x;
-  for (int q = 0; q < m; ++q) {
-    const MapArgs M = maps[q];
-    if (blockIdx.x == 0 && threadIdx.x == 0) *M.err = 0;
-    if (M.tsplit <= 1) continue;
-    const long long n = (long long)M.n_k * M.n_x0;
-    for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += st) M.map[x] = 0;
-  }
-}
-
-__global__ void k_clear(int32_t* map, long long n, unsigned long long* err) {
-  const long long st = (long long)gridDim.x * blockDim.x;
-  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += st) map[x] = 0;
-  if (err && blockIdx.x == 0 && threadIdx.x == 0) *err = 0;
-}
-
-__global__ void k_zero_i32(int32_t* p, int n) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  if (x < n) p[x] = 0;
-}
-
 static fh_status check_launch() { return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE; }
 
 template <int THREADS, bool ALDS>
-static fh_status launch_tiles(const MapArgs& a, int64_t tiles, hipStream_t s) {
-  if (a.lds_bytes > 64 * 1024)
-    (void)hipFuncSetAttribute((const void*)k_hough<THREADS, ALDS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              a.lds_bytes);
-  hipLaunchKernelGGL((k_hough<THREADS, ALDS>), dim3((unsigned)tiles), dim3(THREADS), a.lds_bytes, s, a);
+static void set_lds_attr(int lds) {
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute((const void*)k_queue<THREADS, ALDS>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+int occupancy_grid(int threads, int lds_bytes, int n_units) {
+  int per_cu = 0, dev = 0, cus = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+  const void* fn = threads == 1024 ? (const void*)k_queue<1024, true>
+                   : threads == 512 ? (const void*)k_queue<512, true> : (const void*)k_queue<256, true>;
+  if (lds_bytes > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds_bytes) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  const long long g = (long long)per_cu * cus;
+  return (int)std::min<long long>(g, std::max(n_units, 1));
+}
+
+template <int THREADS, bool ALDS>
+static fh_status launch_queue(const MapArgs& a, const Plan& p, hipStream_t s) {
+  set_lds_attr<THREADS, ALDS>(a.lds_bytes);
+  hipLaunchKernelGGL((k_queue<THREADS, ALDS>), dim3((unsigned)p.grid), dim3(THREADS), a.lds_bytes, s, a,
+                     (const MapArgs*)nullptr, (const Unit*)p.dUnits, (int)p.units.size(), p.dHead);
   return check_launch();
 }
 
 fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStream_t s) {
   MapArgs a = p.args(pk, map);
-  const int64_t tiles = p.n_tiles();
-  if (tiles <= 0 || tiles > 0x7fffffff) return FH_ERANGE;
-  const long long cells = a.tsplit > 1 ? (long long)a.n_k * a.n_x0 : 0;
-  const int cgrid = cells ? (int)std::min<long long>((cells + 255) / 256, 4096) : 1;
-  hipLaunchKernelGGL(k_clear, dim3(cgrid), dim3(256), 0, s, map, cells, a.err);
+  if (p.units.empty()) return FH_EINVAL;
+  const int n_clears = (int)p.clears.size();
+  hipLaunchKernelGGL(k_prologue, dim3((unsigned)std::max(1, std::min(n_clears, 1024))), dim3(256), 0, s, a,
+                     (const MapArgs*)nullptr, 1, (const int4*)p.dClears, n_clears, p.dHead);
   if (check_launch() != FH_OK) return FH_EDEVICE;
   if (a.mode == kModeWindowed) {
     const long long n = (long long)a.n_fft * a.n_words;
@@ -428,8 +491,13 @@ fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStrea
     if (check_launch() != FH_OK) return FH_EDEVICE;
   }
   const int th = p.tile.threads;
-  if (th == 512) return a.a_lds ? launch_tiles<512, true>(a, tiles, s) : launch_tiles<512, false>(a, tiles, s);
-  return a.a_lds ? launch_tiles<256, true>(a, tiles, s) : launch_tiles<256, false>(a, tiles, s);
+  if (p.ev_start && hipEventRecord(p.ev_start, s) != hipSuccess) return FH_EDEVICE;
+  fh_status st;
+  if (th == 1024) st = a.a_lds ? launch_queue<1024, true>(a, p, s) : launch_queue<1024, false>(a, p, s);
+  else if (th == 512) st = a.a_lds ? launch_queue<512, true>(a, p, s) : launch_queue<512, false>(a, p, s);
+  else st = a.a_lds ? launch_queue<256, true>(a, p, s) : launch_queue<256, false>(a, p, s);
+  if (st == FH_OK && p.ev_stop && hipEventRecord(p.ev_stop, s) != hipSuccess) return FH_EDEVICE;
+  return st;
 }
 
 }  // namespace fh
@@ -445,9 +513,10 @@ struct fh_batch_s {
   std::vector<int32_t*> maps;
   std::vector<MapArgs> args;
   MapArgs* d_maps = nullptr;
-  int2* d_queue = nullptr;
+  Unit* d_queue = nullptr;
+  int4* d_clears = nullptr;
   int32_t* d_head = nullptr;
-  int32_t n_queue = 0;
+  int32_t n_queue = 0, n_clears = 0;
   int32_t grid = 0;
   int32_t lds = 0;
   hipStream_t cap = nullptr;
@@ -462,45 +531,20 @@ static void batch_free(fh_batch_s* b) {
   if (b->cap) (void)hipStreamDestroy(b->cap);
   if (b->d_maps) (void)hipFree(b->d_maps);
   if (b->d_queue) (void)hipFree(b->d_queue);
+  if (b->d_clears) (void)hipFree(b->d_clears);
   if (b->d_head) (void)hipFree(b->d_head);
   delete b;
 }
 
-// Estimated cost of one tile: (FFT, row) pairs that can reach it times the
-// mean peaks per FFT, plus the store.
-static double tile_cost(const Plan& p, const MapArgs& a, int tile) {
-  const int nxy = a.tiles_x * a.tiles_y;
-  const int ts = tile / nxy, rem = tile % nxy, rt = rem / a.tiles_x, ct = rem % a.tiles_x;
-  const int r0 = rt * a.rows, nrows = std::min(a.rows, a.n_k - r0);
-  const int c0 = ct * a.cols, c1 = std::min(c0 + a.cols, a.n_x0);
-  const long long i_lo = (long long)a.n_fft * ts / a.tsplit, i_hi = (long long)a.n_fft * (ts + 1) / a.tsplit;
-  const double ppf = (double)a.n_peaks / std::max(1, a.n_fft);
-  double pairs = 0;
-  for (int r = 0; r < nrows; ++r) {
-    const double C = p.C[r0 + r];
-    const double hi_s = p.A[0] - c0 + 1.0;
-    double nf;
-    if (C == 0.0) nf = (double)(i_hi - i_lo);
-    else {
-      const double th = hi_s / C;
-      double lo_t = p.T[i_lo], hi_t = p.T[i_hi - 1];
-      double frac = (th - lo_t) / std::max(hi_t - lo_t, 1e-30);
-      nf = (double)(i_hi - i_lo) * std::min(1.0, std::max(0.0, frac));
-    }
-    pairs += nf * ppf;
-  }
-  const double width_frac = a.mode == kModeWindowed ? std::min(1.0, (double)(c1 - c0) / a.n_x0 * 3.0) : 1.0;
-  return pairs * width_frac + 0.25 * (double)nrows * (c1 - c0);
-}
-
 extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh_peaks* peaks, int32_t* const* maps,
                                      fh_batch_t* out) {
-  if (m < 1 || !plans || !peaks || !maps || !out) return FH_EINVAL;
+  if (m < 1 || m >= kUnitAtomic || !plans || !peaks || !maps || !out) return FH_EINVAL;
   fh_batch_s* b = new (std::nothrow) fh_batch_s();
   if (!b) return FH_ENOMEM;
   b->m = m;
   int lds = 0;
-  std::vector<std::pair<double, int2>> items;
+  double total = 0;
+  bool any_windowed = false;
   for (int i = 0; i < m; ++i) {
     if (!plans[i] || !maps[i] || !peaks[i].row_ptr || peaks[i].n_peaks < 0 || peaks[i].n_peaks >= (1LL << 31) ||
         (peaks[i].n_peaks > 0 && !peaks[i].bin)) {
@@ -509,67 +553,70 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
     }
     const Plan& p = reinterpret_cast<const fh_plan_s*>(plans[i])->p;
     MapArgs a = p.args(peaks[i], maps[i]);
-    if (!a.a_lds) {  // the persistent kernel stages A in LDS
+    // one work-group size for the whole batch (256 threads), A staged in LDS
+    a.lds_bytes = lds_bytes_for_shape(a.n_f, a.rows, a.cols, 1, 256, &a.pitch);
+    a.a_lds = 1;
+    if (a.lds_bytes > kLdsBudget) {
       batch_free(b);
       return FH_ERANGE;
     }
-    // one work-group size for the whole batch: re-derive the LDS need at 256 threads
+    any_windowed |= a.mode == kModeWindowed;
     b->plans.push_back(&p);
     b->peaks.push_back(peaks[i]);
     b->maps.push_back(maps[i]);
     b->args.push_back(a);
     lds = std::max(lds, a.lds_bytes);
-    const int64_t nt = p.n_tiles();
-    for (int64_t t = 0; t < nt; ++t) items.push_back({tile_cost(p, a, (int)t), make_int2(i, (int)t)});
+    total += p.total_cost;
   }
-  if (items.size() >= (size_t)0x7fffffff) {
+  // units of all maps sized against the whole batch, longest first
+  const int resident = occupancy_grid(256, lds, 1 << 30);
+  const double target = total / (4.0 * std::max(resident, 1));
+  std::vector<Unit> units;
+  std::vector<double> cost;
+  std::vector<int4> clears;
+  for (int i = 0; i < m; ++i) split_units(*b->plans[i], i, target, units, cost, clears);
+  std::vector<size_t> order(units.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+  std::vector<Unit> q(order.size());
+  for (size_t i = 0; i < order.size(); ++i) q[i] = units[order[i]];
+  if (q.empty() || q.size() >= (size_t)0x7fffffff) {
     batch_free(b);
     return FH_ERANGE;
   }
-  std::stable_sort(items.begin(), items.end(),
-                   [](const std::pair<double, int2>& x, const std::pair<double, int2>& y) { return x.first > y.first; });
-  std::vector<int2> q(items.size());
-  for (size_t i = 0; i < items.size(); ++i) q[i] = items[i].second;
   b->n_queue = (int32_t)q.size();
+  b->n_clears = (int32_t)clears.size();
   b->lds = lds;
+  b->grid = std::max(1, std::min(resident, b->n_queue));
   if (hipMalloc((void**)&b->d_maps, sizeof(MapArgs) * m) != hipSuccess ||
-      hipMalloc((void**)&b->d_queue, sizeof(int2) * q.size()) != hipSuccess ||
+      hipMalloc((void**)&b->d_queue, sizeof(Unit) * q.size()) != hipSuccess ||
+      hipMalloc((void**)&b->d_clears, sizeof(int4) * std::max<size_t>(1, clears.size())) != hipSuccess ||
       hipMalloc((void**)&b->d_head, sizeof(int32_t)) != hipSuccess) {
     batch_free(b);
     return FH_ENOMEM;
   }
   if (hipMemcpy(b->d_maps, b->args.data(), sizeof(MapArgs) * m, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b->d_queue, q.data(), sizeof(int2) * q.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      hipMemcpy(b->d_queue, q.data(), sizeof(Unit) * q.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      (!clears.empty() &&
+       hipMemcpy(b->d_clears, clears.data(), sizeof(int4) * clears.size(), hipMemcpyHostToDevice) != hipSuccess)) {
     batch_free(b);
     return FH_EDEVICE;
   }
-  if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute((const void*)k_hough_batched<256>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  int per_cu = 0, dev = 0, cus = 0;
-  (void)hipGetDevice(&dev);
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_hough_batched<256>, 256, lds) !=
-          hipSuccess ||
-      per_cu < 1)
-    per_cu = 1;
-  b->grid = std::min<int64_t>((int64_t)per_cu * std::max(cus, 1), b->n_queue);
-  // capture: clear the queue head, per-map clears / rank builds, one persistent kernel
+  set_lds_attr<256, true>(lds);
+  // capture: prologue (queue head, error words, split tiles cleared), rank
+  // structures of windowed maps, one persistent kernel
   if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
     batch_free(b);
     return FH_EDEVICE;
   }
+  MapArgs none{};
   bool ok = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, b->cap, b->d_head, 1);
-    bool any_split = false, any_windowed = false;
-    for (int i = 0; i < m; ++i) {
-      any_split |= b->args[i].tsplit > 1;
-      any_windowed |= b->args[i].mode == kModeWindowed;
-    }
-    hipLaunchKernelGGL(k_clear_batch, dim3(any_split ? 2048 : 1), dim3(256), 0, b->cap, b->d_maps, m);
+    hipLaunchKernelGGL(k_prologue, dim3((unsigned)std::max(1, std::min(b->n_clears, 1024))), dim3(256), 0, b->cap,
+                       none, (const MapArgs*)b->d_maps, m, (const int4*)b->d_clears, b->n_clears, b->d_head);
     if (any_windowed) hipLaunchKernelGGL(k_prepare_batch, dim3(2048), dim3(256), 0, b->cap, b->d_maps, m);
-    hipLaunchKernelGGL(k_hough_batched<256>, dim3(b->grid), dim3(256), lds, b->cap, b->d_maps, b->d_queue,
-                       b->n_queue, b->d_head);
+    hipLaunchKernelGGL((k_queue<256, true>), dim3(b->grid), dim3(256), lds, b->cap, none, (const MapArgs*)b->d_maps,
+                       (const Unit*)b->d_queue, b->n_queue, b->d_head);
     ok = hipStreamEndCapture(b->cap, &b->graph) == hipSuccess;
   }
   if (ok) ok = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;

@@ -1,6 +1,6 @@
 // Internal declarations of the generalized FrequencyHough library (product
 // side only).  The plan holds the host-computed FP64 tables of the canonical
-// index arithmetic and their device copies; the kernels read only these.
+// index arithmetic, their device copies, and the work units of the map.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,19 +12,21 @@
 namespace fh {
 
 constexpr int kWave = 64;
-constexpr int kMaxRowsPerTile = 64;     // rows of one tile (fits one wave's ballot)
+constexpr int kMaxRowsPerTile = 64;     // rows of one tile
 constexpr int kLdsBudget = 160 * 1024;  // gfx950 LDS per work-group
 constexpr int kMaxJTable = 1 << 24;     // largest column->bin table of the windowed mode
+constexpr int kProfileSamples = 128;    // FFT samples of a tile's cost profile
+constexpr int kUnitAtomic = 1 << 30;    // flag bit of a unit's map field: add into the map
 
 enum Mode : int32_t { kModeAuto = 0, kModeWhole = 1, kModeWindowed = 2 };
 
-// Everything a tile of one map needs, by value (kernel argument or queue entry).
+// Everything a tile of one map needs, by value (kernel argument or table entry).
 struct MapArgs {
   const double* A;         // [n_f + 1] column coordinate of each bin edge
   const double* C;         // [n_k] column shift per second of each row
   const double* T;         // [n_fft] time of each FFT
   const int32_t* J;        // [n_J] last bin edge j with A_j >= c (windowed mode)
-  const uint2* rank;       // [n_fft][n_words] (#peaks below word, bit mask) (windowed mode)
+  uint2* rank;             // [n_fft][n_words] (#peaks below word, bit mask) (windowed mode)
   const int32_t* row_ptr;  // [n_fft + 1] peak CSR
   const int32_t* bin;      // [n_peaks]
   int32_t* map;            // [n_k][n_x0]
@@ -35,10 +37,22 @@ struct MapArgs {
   int32_t n_f, n_x0, n_k, n_fft;
   int32_t n_words, n_J;
   int32_t rows, cols, mode;
-  int32_t tiles_x, tiles_y, tsplit;
+  int32_t tiles_x, tiles_y;
   int32_t pitch;           // LDS row pitch of the differential tile (ints)
   int32_t a_lds;           // A table staged in LDS
   int32_t lds_bytes;       // dynamic LDS of one tile
+};
+
+// A unit of work: one tile over an FFT range.  x = map index | kUnitAtomic
+// when the tile is split over several units (they add into a cleared map),
+// y = tile index (row tile * tiles_x + column tile), [z, w) = FFT range.
+using Unit = int4;
+
+// Estimated cost of a tile as a function of its FFT range: cum[q] is the cost
+// of FFTs [lo, lo + (hi - lo) * q / kProfileSamples).
+struct TileProfile {
+  int32_t lo = 0, hi = 0;
+  float cum[kProfileSamples + 1];
 };
 
 struct Plan {
@@ -48,24 +62,39 @@ struct Plan {
   fh_tile_cfg tile{};
   std::vector<double> A, C, T;
   std::vector<int32_t> J;
+  std::vector<TileProfile> prof;  // per tile
+  double total_cost = 0;
+  // work units of a single-map launch, and the tiles to clear before it
+  std::vector<Unit> units;
+  std::vector<double> unit_cost;
+  std::vector<int4> clears;  // (map index, tile index, 0, 0)
   // device
   double *dA = nullptr, *dC = nullptr, *dT = nullptr;
   int32_t* dJ = nullptr;
   uint2* dRank = nullptr;
   unsigned long long* dErr = nullptr;
+  Unit* dUnits = nullptr;
+  int4* dClears = nullptr;
+  int32_t* dHead = nullptr;
+  int32_t grid = 0;  // persistent work-groups of a single-map launch
   int device = 0;
+  int n_cu = 256;
+  hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // optional profiling hook
   MapArgs args(const fh_peaks& pk, int32_t* map) const;
   int64_t n_tiles() const;
 };
 
+int lds_bytes_for_shape(int n_f, int rows, int cols, int a_lds, int threads, int* pitch_out);
+
+// Split the plan's tiles into units of about `target` cost (at most
+// tile.tsplit pieces per tile), append them (map index `mi`) to units/cost and
+// the split tiles to clears.
+void split_units(const Plan& p, int32_t mi, double target, std::vector<Unit>& units, std::vector<double>& cost,
+                 std::vector<int4>& clears);
+
 // implemented in fh_hough.hip
 fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStream_t s);
-int lds_bytes_for(const Plan& p);
-fh_status launch_batched(const MapArgs* d_maps, const int2* d_queue, int32_t n_queue, int32_t* d_head, int lds_max,
-                         int32_t grid, hipStream_t s);
-fh_status launch_prepare(const MapArgs& a, hipStream_t s);
-fh_status launch_zero(unsigned long long* p, int n, hipStream_t s);
-fh_status launch_zero_i32(int32_t* p, int n, hipStream_t s);
+int occupancy_grid(int threads, int lds_bytes, int n_units);
 
 }  // namespace fh
 

@@ -23,10 +23,12 @@ static bool is_finite(double x) { return std::isfinite(x); }
 
 static int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-int lds_bytes_for_shape(int n_f, int rows, int cols, int a_lds, int* pitch_out) {
+int lds_bytes_for_shape(int n_f, int rows, int cols, int a_lds, int threads, int* pitch_out) {
   int pitch = round_up(cols + 1, 4);
   if (pitch_out) *pitch_out = pitch;
-  long long b = (long long)rows * pitch * 4 + (long long)rows * 8 * 2 + (long long)rows * 4 * 2 + 256;
+  // [A][C rows][per-wave scratch 1040 B][ia, ib rows][16 + 4 ints][D rows x pitch]
+  long long b = (long long)rows * pitch * 4 + (long long)rows * 8 + (long long)(threads / 64) * 1040 +
+                (long long)rows * 8 + 80 + 16;
   if (a_lds) b += (long long)(n_f + 1) * 8;
   return b > (1LL << 30) ? (1 << 30) : (int)b;
 }
@@ -56,59 +58,177 @@ MapArgs Plan::args(const fh_peaks& pk, int32_t* map) const {
   a.mode = tile.mode;
   a.tiles_x = (n_x0 + tile.cols - 1) / tile.cols;
   a.tiles_y = (desc.n_k + tile.rows - 1) / tile.rows;
-  a.tsplit = tile.tsplit;
-  a.a_lds = (lds_bytes_for_shape(n_f, tile.rows, tile.cols, 1, nullptr) <= kLdsBudget) ? 1 : 0;
-  a.lds_bytes = lds_bytes_for_shape(n_f, tile.rows, tile.cols, a.a_lds, &a.pitch);
+  a.a_lds = (lds_bytes_for_shape(n_f, tile.rows, tile.cols, 1, tile.threads, nullptr) <= kLdsBudget) ? 1 : 0;
+  a.lds_bytes = lds_bytes_for_shape(n_f, tile.rows, tile.cols, a.a_lds, tile.threads, &a.pitch);
   return a;
 }
 
 int64_t Plan::n_tiles() const {
   int64_t tx = (n_x0 + tile.cols - 1) / tile.cols;
   int64_t ty = (desc.n_k + tile.rows - 1) / tile.rows;
-  return tx * ty * tile.tsplit;
+  return tx * ty;
 }
 
 // Automatic tile shape (the autotuner may override it through fh_tile_cfg).
 static fh_tile_cfg auto_tile(const Plan& p) {
   fh_tile_cfg c{};
   const int nk = p.desc.n_k;
+  c.tsplit = 64;
   if (p.n_x0 <= 6144 || p.n_J == 0) {
     c.mode = kModeWhole;
     c.threads = 256;
     c.cols = std::min(p.n_x0, 8192);
     int pitch = round_up(c.cols + 1, 4);
-    int rows = (32 * 1024) / (pitch * 4);
+    int rows = (40 * 1024) / (pitch * 4);
     rows = std::max(1, std::min(rows, kMaxRowsPerTile));
     while (rows & (rows - 1)) rows &= rows - 1;  // power of two
-    rows = std::min(rows, nk);
-    // enough tiles to fill the chip: shrink the band, then split time
-    int64_t tx = (p.n_x0 + c.cols - 1) / c.cols;
-    while (rows > 4 && tx * ((nk + rows - 1) / rows) < 512) rows /= 2;
-    c.rows = rows;
-    int64_t tiles = tx * ((nk + rows - 1) / rows);
-    int ts = 1;
-    while (tiles * ts < 512 && ts < 64 && (int64_t)p.desc.n_fft / (ts * 2) >= 64) ts *= 2;
-    c.tsplit = ts;
+    c.rows = std::min(rows, nk);
   } else {
     c.mode = kModeWindowed;
     c.threads = 512;
     c.rows = 1;
-    c.cols = std::min(p.n_x0, 16384);
-    c.tsplit = 1;
+    // widest tile that leaves room for the A table in LDS
+    int cols = 32768;
+    while (cols > 1024 && lds_bytes_for_shape(p.n_f, 1, cols, 1, c.threads, nullptr) > kLdsBudget) cols -= 1024;
+    int ntx = (p.n_x0 + cols - 1) / cols;
+    c.cols = (p.n_x0 + ntx - 1) / ntx;
   }
   return c;
+}
+
+// FFT range [ia, ib) that can bring the band's image onto columns [c0, c1)
+// at row shift C per second (host twin of the kernel's range, for costs).
+static void host_fft_range(const Plan& p, double C, int c0, int c1, int* ia, int* ib) {
+  const int nf = p.desc.n_fft;
+  const double hi_s = p.A[0] - (double)c0 + 1.0;
+  const double lo_s = p.A[p.n_f] - (double)c1 - 1.0;
+  if (C == 0.0) {
+    const bool ok = lo_s <= 0.0 && 0.0 <= hi_s;
+    *ia = 0;
+    *ib = ok ? nf : 0;
+    return;
+  }
+  const double tl = lo_s / C, th = hi_s / C;
+  *ia = (int)(std::lower_bound(p.T.begin(), p.T.end(), tl) - p.T.begin());
+  *ib = (int)(std::upper_bound(p.T.begin(), p.T.end(), th) - p.T.begin());
+  if (*ib < *ia) *ib = *ia;
+}
+
+// Relative cost model: one unit per (peak, row) pair handled, about 12.5
+// peaks per 160 bins of noise peakmap (threshold 2.5), one unit per
+// (row, FFT) item of the windowed mode.
+static constexpr double kPeakDensity = 0.08;
+
+static void build_profiles(Plan& p) {
+  const int tx = (p.n_x0 + p.tile.cols - 1) / p.tile.cols;
+  const int ty = (p.desc.n_k + p.tile.rows - 1) / p.tile.rows;
+  p.prof.assign((size_t)tx * ty, TileProfile());
+  p.total_cost = 0;
+  std::vector<int> ia(p.tile.rows), ib(p.tile.rows);
+  for (int rt = 0; rt < ty; ++rt) {
+    const int r0 = rt * p.tile.rows, nrows = std::min(p.tile.rows, p.desc.n_k - r0);
+    for (int ct = 0; ct < tx; ++ct) {
+      const int c0 = ct * p.tile.cols, c1 = std::min(c0 + p.tile.cols, p.n_x0);
+      TileProfile& pr = p.prof[(size_t)rt * tx + ct];
+      int lo = p.desc.n_fft, hi = 0;
+      for (int r = 0; r < nrows; ++r) {
+        host_fft_range(p, p.C[r0 + r], c0, c1, &ia[r], &ib[r]);
+        if (ia[r] < ib[r]) {
+          lo = std::min(lo, ia[r]);
+          hi = std::max(hi, ib[r]);
+        }
+      }
+      if (p.tile.mode == kModeWhole && rt == 0 && ct == 0) {  // this tile also counts bad peaks
+        lo = 0;
+        hi = p.desc.n_fft;
+      }
+      if (hi < lo) hi = lo;
+      pr.lo = lo;
+      pr.hi = hi;
+      pr.cum[0] = 0;
+      for (int q = 0; q < kProfileSamples; ++q) {
+        const int a = lo + (int)((int64_t)(hi - lo) * q / kProfileSamples);
+        const int b = lo + (int)((int64_t)(hi - lo) * (q + 1) / kProfileSamples);
+        double c = 0;
+        if (b > a) {
+          const int i = (a + b) / 2;
+          if (p.tile.mode == kModeWhole) {
+            int act = 0;
+            for (int r = 0; r < nrows; ++r) act += (ia[r] <= i && i < ib[r]);
+            c = kPeakDensity * p.n_f * (act + 1);
+          } else {
+            for (int r = 0; r < nrows; ++r) {
+              if (!(ia[r] <= i && i < ib[r])) continue;
+              const double sh = p.C[r0 + r] * p.T[i];
+              const double y0 = c0 + sh - 1.0, y1 = c1 + sh + 1.0;
+              int jb = y0 < 0 ? p.n_f - 1 : (y0 >= p.n_J - 1 ? -1 : std::min(p.J[(int)y0], p.n_f - 1));
+              int ja = y1 <= 0 ? 0 : (y1 >= p.n_J - 1 ? p.J[p.n_J - 1] : p.J[(int)std::ceil(y1)]);
+              ja = std::max(ja, 0);
+              c += 1.0 + kPeakDensity * std::max(0, jb - ja + 1);
+            }
+          }
+          c *= (double)(b - a);
+        }
+        pr.cum[q + 1] = pr.cum[q] + (float)c;
+      }
+      p.total_cost += pr.cum[kProfileSamples];
+    }
+  }
+}
+
+void split_units(const Plan& p, int32_t mi, double target, std::vector<Unit>& units, std::vector<double>& cost,
+                 std::vector<int4>& clears) {
+  const int tx = (p.n_x0 + p.tile.cols - 1) / p.tile.cols;
+  const int ty = (p.desc.n_k + p.tile.rows - 1) / p.tile.rows;
+  for (int t = 0; t < tx * ty; ++t) {
+    const TileProfile& pr = p.prof[t];
+    const int rt = t / tx, ct = t % tx;
+    const int nrows = std::min(p.tile.rows, p.desc.n_k - rt * p.tile.rows);
+    const int W = std::min(p.tile.cols, p.n_x0 - ct * p.tile.cols);
+    const double work = pr.cum[kProfileSamples];
+    int pieces = (int)std::min<double>(p.tile.tsplit, std::max(1.0, std::floor(work / std::max(target, 1.0) + 0.5)));
+    pieces = std::max(1, std::min(pieces, std::max(1, pr.hi - pr.lo)));
+    const double store = 0.5 * nrows * W * (pieces > 1 ? 3.0 : 1.0);
+    if (pieces == 1) {
+      units.push_back(make_int4(mi, t, pr.lo, pr.hi));
+      cost.push_back(work + store);
+      continue;
+    }
+    clears.push_back(make_int4(mi, t, 0, 0));
+    int prev = pr.lo;
+    int q = 0;
+    for (int k = 1; k <= pieces; ++k) {
+      int cut;
+      if (k == pieces) {
+        cut = pr.hi;
+      } else {
+        const double want = work * k / pieces;
+        while (q < kProfileSamples && pr.cum[q + 1] < want) ++q;
+        const double seg = pr.cum[q + 1] - pr.cum[q];
+        const double fr = seg > 0 ? (want - pr.cum[q]) / seg : 0.0;
+        const int a = pr.lo + (int)((int64_t)(pr.hi - pr.lo) * q / kProfileSamples);
+        const int b = pr.lo + (int)((int64_t)(pr.hi - pr.lo) * (q + 1) / kProfileSamples);
+        cut = std::max(prev, std::min(pr.hi, a + (int)((b - a) * fr)));
+      }
+      if (cut > prev) {
+        units.push_back(make_int4(mi | kUnitAtomic, t, prev, cut));
+        cost.push_back(work / pieces + store / pieces);
+      }
+      prev = cut;
+    }
+  }
 }
 
 static fh_status validate_tile(const Plan& p, fh_tile_cfg* c) {
   if (c->mode != kModeWhole && c->mode != kModeWindowed) return FH_EINVAL;
   if (c->mode == kModeWindowed && p.n_J == 0) return FH_EINVAL;
-  if (c->threads != 256 && c->threads != 512) return FH_EINVAL;
+  if (c->threads != 256 && c->threads != 512 && c->threads != 1024) return FH_EINVAL;
   if (c->rows < 1 || c->rows > kMaxRowsPerTile) return FH_EINVAL;
   if (c->cols < 1) return FH_EINVAL;
   if (c->cols > p.n_x0) c->cols = p.n_x0;
   if (c->rows > p.desc.n_k) c->rows = p.desc.n_k;
-  if (c->tsplit < 1 || c->tsplit > p.desc.n_fft) return FH_EINVAL;
-  if (lds_bytes_for_shape(p.n_f, c->rows, c->cols, 0, nullptr) > kLdsBudget) return FH_ERANGE;
+  if (c->tsplit < 1 || c->tsplit > 1024) return FH_EINVAL;
+  if (lds_bytes_for_shape(p.n_f, c->rows, c->cols, 0, c->threads, nullptr) > kLdsBudget) return FH_ERANGE;
   return FH_OK;
 }
 
@@ -119,6 +239,12 @@ static void free_dev(Plan& p) {
   if (p.dJ) (void)hipFree(p.dJ);
   if (p.dRank) (void)hipFree(p.dRank);
   if (p.dErr) (void)hipFree(p.dErr);
+  if (p.dUnits) (void)hipFree(p.dUnits);
+  if (p.dClears) (void)hipFree(p.dClears);
+  if (p.dHead) (void)hipFree(p.dHead);
+  p.dUnits = nullptr;
+  p.dClears = nullptr;
+  p.dHead = nullptr;
   p.dA = p.dC = p.dT = nullptr;
   p.dJ = nullptr;
   p.dRank = nullptr;
@@ -253,6 +379,32 @@ extern "C" fh_status fh_plan(const fh_map_desc* d, const fh_tile_cfg* cfg, fh_pl
   }
   p.tile = c;
   (void)hipGetDevice(&p.device);
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p.device) == hipSuccess && cus > 0)
+      p.n_cu = cus;
+  }
+  build_profiles(p);
+  {
+    int pitch;
+    const int a_lds = lds_bytes_for_shape(n_f, c.rows, c.cols, 1, c.threads, nullptr) <= kLdsBudget;
+    const int lds = lds_bytes_for_shape(n_f, c.rows, c.cols, a_lds, c.threads, &pitch);
+    const int resident = occupancy_grid(c.threads, lds, 1 << 30);
+    split_units(p, 0, p.total_cost / (4.0 * std::max(resident, 1)), p.units, p.unit_cost, p.clears);
+    // longest first
+    std::vector<size_t> order(p.units.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return p.unit_cost[x] > p.unit_cost[y]; });
+    std::vector<Unit> u(order.size());
+    std::vector<double> uc(order.size());
+    for (size_t i = 0; i < order.size(); ++i) {
+      u[i] = p.units[order[i]];
+      uc[i] = p.unit_cost[order[i]];
+    }
+    p.units.swap(u);
+    p.unit_cost.swap(uc);
+    p.grid = std::max(1, std::min<int>(resident, (int)p.units.size()));
+  }
   st = upload(&p.dA, p.A.data(), p.A.size());
   if (st == FH_OK) st = upload(&p.dC, p.C.data(), p.C.size());
   if (st == FH_OK) st = upload(&p.dT, p.T.data(), p.T.size());
@@ -260,6 +412,9 @@ extern "C" fh_status fh_plan(const fh_map_desc* d, const fh_tile_cfg* cfg, fh_pl
   if (st == FH_OK && c.mode == kModeWindowed)
     st = upload<uint2>(&p.dRank, nullptr, (size_t)d->n_fft * (size_t)p.n_words);
   if (st == FH_OK) st = upload<unsigned long long>(&p.dErr, nullptr, 1);
+  if (st == FH_OK) st = upload<Unit>(&p.dUnits, p.units.data(), p.units.size());
+  if (st == FH_OK) st = upload<int4>(&p.dClears, p.clears.data(), p.clears.size());
+  if (st == FH_OK) st = upload<int32_t>(&p.dHead, nullptr, 1);
   if (st == FH_OK && hipMemset(p.dErr, 0, sizeof(unsigned long long)) != hipSuccess) st = FH_EDEVICE;
   if (st != FH_OK) {
     free_dev(p);
@@ -309,6 +464,14 @@ extern "C" fh_status fh_hough(fh_plan_t h, const fh_peaks* pk, int32_t* map, voi
   if (pk->n_peaks > 0 && !pk->bin) return FH_EINVAL;
   const Plan& p = reinterpret_cast<Plan&>(*h);
   return launch_hough(p, *pk, map, (hipStream_t)stream);
+}
+
+extern "C" fh_status fh_plan_set_events(fh_plan_t h, void* start, void* stop) {
+  if (!h || (!start) != (!stop)) return FH_EINVAL;
+  Plan& p = reinterpret_cast<Plan&>(*h);
+  p.ev_start = (hipEvent_t)start;
+  p.ev_stop = (hipEvent_t)stop;
+  return FH_OK;
 }
 
 extern "C" fh_status fh_device_errors(fh_plan_t h, void* stream, uint64_t* out) {

@@ -58,6 +58,7 @@ SIGNATURES = {
     "fh_plan_destroy": (None, [C.c_void_p]),
     "fh_hough": (C.c_int, [C.c_void_p, C.POINTER(Peaks), C.c_void_p, C.c_void_p]),
     "fh_device_errors": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)]),
+    "fh_plan_set_events": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fh_batch_create": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(Peaks), C.POINTER(C.c_void_p),
                                   C.POINTER(C.c_void_p)]),
     "fh_batch_launch": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -194,6 +195,13 @@ def fh_hough(plan: Plan, row_ptr, bin_, out=None, stream=None):
     pk = peaks_struct(row_ptr, bin_)
     _check(lib().fh_hough(plan.handle, C.byref(pk), C.c_void_p(_ptr(out)), _stream(stream)), "fh_hough")
     return out
+
+
+def fh_plan_set_events(plan: Plan, start=None, stop=None):
+    """start/stop: torch.cuda.Event(enable_timing=True) or None (clears)."""
+    a = C.c_void_p(int(start.cuda_event)) if start is not None else None
+    b = C.c_void_p(int(stop.cuda_event)) if stop is not None else None
+    _check(lib().fh_plan_set_events(plan.handle, a, b), "fh_plan_set_events")
 
 
 def fh_device_errors(plan: Plan, stream=None) -> int:

@@ -216,3 +216,68 @@ def test_large_map_sampled_rows(dev, oracle):
     got = out[rows].cpu().numpy()
     assert_maps_equal(got, ref, "large map rows")
     assert (out >= 0).all().item()
+
+
+def _batched_inputs(dev, specs):
+    import torch
+    from paper_1810_09784_amd import fh
+    plans, peaks, pms = [], [], []
+    for s in specs:
+        pm = S.make_peakmap(s)
+        pms.append(pm)
+        plans.append(fh.Plan.from_spec(s))
+        peaks.append(_to_dev(pm, dev))
+    return plans, peaks, pms
+
+
+def test_batched_uneven_maps_exact(dev, oracle):
+    # 48 maps: n in {2,2.5,3,4,5,7} x T_FFT in {1,2,4,8} s x 2 seeds, 64 Hz bands,
+    # 2 h - 3 days, 64-1024 k rows; one persistent graph launch
+    import torch
+    from paper_1810_09784_amd import fh
+    specs = S.cfg_batched()
+    plans, peaks, pms = _batched_inputs(dev, specs)
+    maps = [torch.full((p.n_k, p.n_x0), -7, dtype=torch.int32, device=dev) for p in plans]
+    ref_maps = [torch.full_like(m, -9) for m in maps]
+    batch = fh.Batch(plans, peaks, maps)
+    plain = fh.Batch(plans, peaks, ref_maps)
+    plain.launch_plain()
+    torch.cuda.synchronize()
+    for rep in range(3):  # graph replays, with eager work and syncs in between
+        for m in maps:
+            m.fill_(-7)
+        torch.cuda.synchronize()
+        batch.launch()
+        torch.cuda.synchronize()
+        for q in range(len(maps)):
+            assert torch.equal(maps[q], ref_maps[q]), (rep, specs[q].name)
+    for q, (s, p) in enumerate(zip(specs, plans)):
+        assert fh.fh_device_errors(p) == 0
+        rng = np.random.default_rng(q)
+        rows = sorted(set([0, s.n_k - 1] + list(rng.integers(0, s.n_k, 3))))
+        ref = oracle.hough(oracle.Desc.from_spec(s), pms[q].row_ptr, pms[q].bin, rows=rows)
+        assert_maps_equal(maps[q][rows].cpu().numpy(), ref, s.name)
+    batch.destroy()
+    plain.destroy()
+
+
+def test_batched_small_maps_full_compare(dev, oracle):
+    import torch
+    from paper_1810_09784_amd import fh
+    rng = np.random.default_rng(90)
+    specs = []
+    for q in range(12):
+        specs.append(S.cfg_tiny(rng, n_fft=int(rng.integers(1, 300)), n_f=int(rng.integers(3, 200)),
+                                n_k=int(rng.integers(1, 50)), n=float(rng.choice([2.0, 3.0, 5.0])),
+                                tfft=float(rng.choice([1.0, 2.0])), f_min=float(rng.integers(100, 900)),
+                                kscale=float(rng.choice([0.01, 0.1, 1.0]))))
+    plans, peaks, pms = _batched_inputs(dev, specs)
+    # mixed tile shapes in one batch, including windowed and time-split plans
+    tiles = [None, TILES[1], TILES[2], TILES[5], TILES[6]]
+    plans = [fh.Plan.from_spec(s, tile=tiles[q % len(tiles)]) for q, s in enumerate(specs)]
+    maps = [torch.full((p.n_k, p.n_x0), -7, dtype=torch.int32, device=dev) for p in plans]
+    fh.fh_hough_batched(plans, peaks, maps)
+    torch.cuda.synchronize()
+    for q, s in enumerate(specs):
+        ref = oracle.hough(oracle.Desc.from_spec(s), pms[q].row_ptr, pms[q].bin)
+        assert_maps_equal(maps[q].cpu().numpy(), ref, f"{s.name} tile={plans[q].tile}")
