@@ -26,6 +26,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstdint>
 #include <cstring>
 #include <new>
@@ -45,7 +46,7 @@ __device__ __forceinline__ int cvt_sat_i32(double x) {
 }
 
 __device__ __forceinline__ bool is_negative(double x) {
-  return (long long)__builtin_bit_cast(unsigned long long, x) < 0;
+  return (int)(__builtin_bit_cast(unsigned long long, x) >> 32) < 0;
 }
 
 // Inclusive prefix sum over the 64 lanes of a wavefront (DPP row shifts and
@@ -63,33 +64,53 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // One (peak, row) pair: the +1/-1 edges of its clipped interval in the tile.
-// Drow points at the tile row; the slot at index (c1 - c0) absorbs right edges
-// that fall outside the tile.
-__device__ __forceinline__ void edge_update(int* Drow, double C, double T, double a_lo, double a_hi, int c0, int c1,
-                                            bool valid) {
+// Drow points at the tile row (its slot at index c1 - c0 absorbs right edges
+// outside the tile); an empty or invalid interval sends both edges to the
+// lane's own discard word, so the update needs no branch.
+__device__ __forceinline__ void edge_update(int* Drow, int* discard, double C, double T, double a_lo, double a_hi,
+                                            int c0, int c1, bool valid) {
   const double u_lo = __builtin_fma(-C, T, a_lo);
   const double u_hi = __builtin_fma(-C, T, a_hi);
   // max(floor(u), c0) == max(trunc(u), c0) for c0 >= 0; floor(u_hi) < 0 iff u_hi < 0
   const int lo = max(cvt_sat_i32(u_lo), c0);
   const int hi = min(cvt_sat_i32(u_hi), c1 - 1);
-  if (valid && !is_negative(u_hi) && lo <= hi) {
-    atomicAdd(&Drow[lo - c0], 1);
-    atomicAdd(&Drow[hi + 1 - c0], -1);
-  }
+  const bool ok = valid && !is_negative(u_hi) && lo <= hi;
+  int* plo = ok ? Drow + (lo - c0) : discard;
+  int* phi = ok ? Drow + (hi + 1 - c0) : discard;
+  atomicAdd(plo, 1);
+  atomicAdd(phi, -1);
 }
 
+// Global-memory views of the map's arrays (address space 1), so that loads
+// and stores are global (not flat) instructions and never ordered against LDS.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+struct GMap {
+  gptr<const double> A, C, T;
+  gptr<const int> J, row_ptr, bin;
+  gptr<const unsigned long long> rank;  // (bit mask << 32) | peaks below the word
+  gptr<int> map;
+  __device__ explicit GMap(const MapArgs& M)
+      : A((gptr<const double>)M.A), C((gptr<const double>)M.C), T((gptr<const double>)M.T),
+        J((gptr<const int>)M.J), row_ptr((gptr<const int>)M.row_ptr), bin((gptr<const int>)M.bin),
+        rank((gptr<const unsigned long long>)M.rank), map((gptr<int>)M.map) {}
+};
+
 // rank(i, j): number of peaks of FFT i with bin < j (0 <= j <= n_f).
-__device__ __forceinline__ int peak_rank(const MapArgs& M, int i, int j) {
-  const uint2 e = M.rank[(size_t)i * M.n_words + (j >> 5)];
+__device__ __forceinline__ int peak_rank(const MapArgs& M, const GMap& G, int i, int j) {
+  const unsigned long long e = G.rank[(size_t)(j >> 5) * M.n_fft + i];
   const unsigned below = (j & 31) ? ((1u << (j & 31)) - 1u) : 0u;
-  return (int)e.x + __builtin_popcount(e.y & below);
+  return (int)(unsigned)e + __builtin_popcount((unsigned)(e >> 32) & below);
 }
 
 // FFT range [ia, ib) whose shift s = C T_i can bring the band's image
 // (A_{n_f} - s, A_0 - s] onto columns [c0, c1); one column of margin.
-__device__ void fft_range(const MapArgs& M, double C, int c0, int c1, int i_lo, int i_hi, int* ia, int* ib) {
-  const double hi_s = M.A[0] - (double)c0 + 1.0;
-  const double lo_s = M.A[M.n_f] - (double)c1 - 1.0;
+__device__ void fft_range(const MapArgs& M, const GMap& G, double C, int c0, int c1, int i_lo, int i_hi, int* ia,
+                          int* ib) {
+  const double hi_s = G.A[0] - (double)c0 + 1.0;
+  const double lo_s = G.A[M.n_f] - (double)c1 - 1.0;
   if (C == 0.0) {
     const bool ok = lo_s <= 0.0 && 0.0 <= hi_s;
     *ia = i_lo;
@@ -109,13 +130,13 @@ __device__ void fft_range(const MapArgs& M, double C, int c0, int c1, int i_lo, 
     int x = i_lo, y = i_hi;
     while (x < y) {
       int m = (x + y) >> 1;
-      if (M.T[m] < tl) x = m + 1; else y = m;
+      if (G.T[m] < tl) x = m + 1; else y = m;
     }
     a = x;
     y = i_hi;
     while (x < y) {
       int m = (x + y) >> 1;
-      if (M.T[m] <= th) x = m + 1; else y = m;
+      if (G.T[m] <= th) x = m + 1; else y = m;
     }
     b = x;
   }
@@ -123,15 +144,15 @@ __device__ void fft_range(const MapArgs& M, double C, int c0, int c1, int i_lo, 
   *ib = b;
 }
 
-// Inclusive max-scan over the wavefront (same DPP pattern as the sum).
-__device__ __forceinline__ int wave_incl_max(int x) {
-  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x111, 0xf, 0xf, false));
-  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x112, 0xf, 0xf, false));
-  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x114, 0xf, 0xf, false));
-  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x118, 0xf, 0xf, false));
-  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x142, 0xa, 0xf, false));
-  x = max(x, __builtin_amdgcn_update_dpp(-1, x, 0x143, 0xc, 0xf, false));
-  return x;
+// Maximum over the wavefront (DPP, VALU only).
+__device__ __forceinline__ int wave_max(int x) {
+  x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x111, 0xf, 0xf, false));  // row_shr:1
+  x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x112, 0xf, 0xf, false));  // row_shr:2
+  x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x114, 0xf, 0xf, false));  // row_shr:4
+  x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x118, 0xf, 0xf, false));  // row_shr:8
+  x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return __builtin_amdgcn_readlane(x, 63);
 }
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -151,8 +172,9 @@ static_assert(sizeof(WaveScratch) == 1040, "per-wave LDS scratch size is part of
 // One unit: tile `tile` of map M over FFTs [i_lo, i_hi); `atomic` when the
 // tile is split over several units (the map region was cleared beforehand).
 template <int THREADS, bool ALDS>
-__device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool atomic, char* smem) {
+__device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool atomic, bool load_a, char* smem) {
   constexpr int NW = THREADS / kWave;
+  const GMap G(M);
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wave = uniform(tid >> 6);
@@ -174,17 +196,17 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
   int* ib_s = ia_s + M.rows;
   int* wtot = ib_s + M.rows;  // per-wave partial sums (16 ints)
   int* flags = wtot + 16;     // [0]: ib non-increasing over the rows, [1] [2]: union FFT range
-  int* D = flags + 4;
-  const double* A = ALDS ? A_s : M.A;
+  int* discard = flags + 4 + lane;  // per-lane sink of empty intervals (64 ints)
+  int* D = flags + 4 + kWave;
 
-  if (ALDS)
-    for (int j = tid; j <= M.n_f; j += THREADS) A_s[j] = M.A[j];
+  if (ALDS && load_a)
+    for (int j = tid; j <= M.n_f; j += THREADS) A_s[j] = G.A[j];
   for (int x = tid; x < nrows * pitch; x += THREADS) D[x] = 0;
   if (tid < nrows) {
-    const double C = M.C[r0 + tid];
+    const double C = G.C[r0 + tid];
     C_s[tid] = C;
     int a, b;
-    fft_range(M, C, c0, c1, i_lo, i_hi, &a, &b);
+    fft_range(M, G, C, c0, c1, i_lo, i_hi, &a, &b);
     ia_s[tid] = a;
     ib_s[tid] = b;
   }
@@ -215,8 +237,9 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
     for (int f0 = i_start + wave * kWave; f0 < i_end; f0 += NW * kWave) {
       const int nb = min(kWave, i_end - f0);
       const int fi = f0 + min(lane, nb - 1);
-      const int rp_l = min(max(M.row_ptr[f0 + min(lane, nb)], 0), M.n_peaks);
-      const int rp_e = uniform(min(max(M.row_ptr[f0 + nb], 0), M.n_peaks));
+      const int rp_l = min(max(G.row_ptr[f0 + min(lane, nb)], 0), M.n_peaks);
+      const int rp_e = uniform(min(max(G.row_ptr[f0 + nb], 0), M.n_peaks));
+      const double Tf = G.T[fi];
       int rb = nrows;
       if (mono) {
         int u = 0, w = nrows;  // first r with ib_r <= fi
@@ -229,7 +252,7 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
       wave_sync_lds();
       S.rp[lane] = rp_l;
       if (lane == 0) S.rp[kWave] = rp_e;
-      S.T[lane] = M.T[fi];
+      S.T[lane] = Tf;
       S.rb[lane] = lane < nb ? rb : 0;
       wave_sync_lds();
       const int Pa = uniform(S.rp[0]);
@@ -238,6 +261,7 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
         const int p = pc + lane;
         const bool pv = p < Pb;
         const int pcl = pv ? p : Pa;
+        const int j = G.bin[pcl];
         // block FFT of the peak: last k < nb with rp[k] <= p
         int u = 0, w = nb - 1;
         while (u < w) {
@@ -245,14 +269,17 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
           if (S.rp[mid] <= pcl) u = mid; else w = mid - 1;
         }
         const double T = S.T[u];
-        const int j = M.bin[pcl];
         const bool jv = pv && (unsigned)j < (unsigned)M.n_f;
         if (count_bad && pv && !jv) atomicAdd(M.err, 1ull);
         const int jc = jv ? j : 0;
-        const double a_hi = A[jc];
-        const double a_lo = A[jc + 1];
+        const double a_hi = ALDS ? A_s[jc] : G.A[jc];
+        const double a_lo = ALDS ? A_s[jc + 1] : G.A[jc + 1];
         const int rbl = jv ? S.rb[u] : 0;
-        for (int r = 0; r < rbl; ++r) edge_update(D + r * pitch, C_s[r], T, a_lo, a_hi, c0, c1, true);
+        const int rmax = wave_max(rbl);
+        for (int r = 0; r < rmax; ++r) {
+          const double C = G.C[r0 + r];  // uniform: a scalar load, no LDS ordering
+          edge_update(D + r * pitch, discard, C, T, a_lo, a_hi, c0, c1, r < rbl);
+        }
       }
     }
   } else {
@@ -260,13 +287,13 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
     // the tile's columns and walks them (four loads in flight per lane).
     for (int rl = 0; rl < nrows; ++rl) {
       const int ia = ia_s[rl], ib = ib_s[rl];
-      const double C = C_s[rl];
+      const double C = G.C[r0 + rl];
       int* Drow = D + rl * pitch;
       for (int qb = ia + wave * kWave; qb < ib; qb += NW * kWave) {
         const int i = qb + lane;
         const bool iv = i < ib;
         const int ic = iv ? i : ia;
-        const double T = M.T[ic];
+        const double T = G.T[ic];
         const double s = C * T;
         // a superset of the bins whose image can meet [c0, c1): A_j >= c0 + s and
         // A_{j+1} < c1 + s, each widened by one column against rounding
@@ -275,27 +302,49 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
         int jb, ja;
         if (y0 < 0.0) jb = M.n_f - 1;
         else if (y0 >= (double)(M.n_J - 1)) jb = -1;
-        else jb = min(M.J[(int)y0], M.n_f - 1);
+        else jb = min(G.J[(int)y0], M.n_f - 1);
         if (y1 <= 0.0) ja = 0;
-        else if (y1 >= (double)(M.n_J - 1)) ja = M.J[M.n_J - 1];
-        else ja = M.J[(int)__builtin_ceil(y1)];
+        else if (y1 >= (double)(M.n_J - 1)) ja = G.J[M.n_J - 1];
+        else ja = G.J[(int)__builtin_ceil(y1)];
         ja = max(ja, 0);
-        const int base = min(max(M.row_ptr[ic], 0), M.n_peaks);
-        const int end = min(max(M.row_ptr[ic + 1], base), M.n_peaks);
+        const int base = min(max(G.row_ptr[ic], 0), M.n_peaks);
+        const int end = min(max(G.row_ptr[ic + 1], base), M.n_peaks);
         int pa = 0, pe = 0;
         if (iv && jb >= ja) {
-          pa = min(base + peak_rank(M, ic, ja), end);
-          pe = max(min(base + peak_rank(M, ic, jb + 1), end), pa);
+          pa = min(base + peak_rank(M, G, ic, ja), end);
+          pe = max(min(base + peak_rank(M, G, ic, jb + 1), end), pa);
         }
-        for (int p = pa; p < pe; p += 4) {
-          const int q1 = min(p + 1, pe - 1), q2 = min(p + 2, pe - 1), q3 = min(p + 3, pe - 1);
-          const int j0 = M.bin[p], j1 = M.bin[q1], j2 = M.bin[q2], j3 = M.bin[q3];
-          const int jj[4] = {j0, j1, j2, j3};
+        // 16-byte aligned groups of four bins, four groups in flight per lane
+        for (int g = pa & ~3; g < pe; g += 16) {
+          int jj[16];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const bool jv = (p + u < pe) && (unsigned)jj[u] < (unsigned)M.n_f;
-            const int jc = jv ? jj[u] : 0;
-            edge_update(Drow, C, T, A[jc + 1], A[jc], c0, c1, jv);
+          for (int k = 0; k < 4; ++k) {
+            const int q = g + 4 * k;
+            if (q + 3 < M.n_peaks && q < pe) {
+              const v4i v = *(gptr<const v4i>)(G.bin + q);
+              jj[4 * k] = v.x;
+              jj[4 * k + 1] = v.y;
+              jj[4 * k + 2] = v.z;
+              jj[4 * k + 3] = v.w;
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) jj[4 * k + e] = G.bin[min(q + e, M.n_peaks - 1)];
+            }
+          }
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            double alo[4], ahi[4];
+            bool vv[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {  // table reads of four peaks before their atomics
+              const int q = g + 4 * h + e;
+              vv[e] = q >= pa && q < pe && (unsigned)jj[4 * h + e] < (unsigned)M.n_f;
+              const int jc = vv[e] ? jj[4 * h + e] : 0;
+              ahi[e] = ALDS ? A_s[jc] : G.A[jc];
+              alo[e] = ALDS ? A_s[jc + 1] : G.A[jc + 1];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) edge_update(Drow, discard, C, T, alo[e], ahi[e], c0, c1, vv[e]);
           }
         }
       }
@@ -304,19 +353,18 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
   __syncthreads();
 
   // prefix sums along x0 and the store
-  const bool accumulate = atomic;
   if (nrows >= NW) {
     for (int rl = wave; rl < nrows; rl += NW) {
       const int* Drow = D + rl * pitch;
-      int32_t* out = M.map + (size_t)(r0 + rl) * M.n_x0 + c0;
+      gptr<int> out = G.map + (size_t)(r0 + rl) * M.n_x0 + c0;
       int carry = 0;
       for (int x0 = 0; x0 < W; x0 += kWave) {
         const int x = x0 + lane;
         const int v = x < W ? Drow[x] : 0;
         const int s = wave_incl_scan(v) + carry;
         if (x < W) {
-          if (accumulate) {
-            if (s) atomicAdd(&out[x], s);
+          if (atomic) {
+            if (s) __hip_atomic_fetch_add(out + x, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           } else {
             out[x] = s;
           }
@@ -340,14 +388,14 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
       __syncthreads();
       int carry = 0;
       for (int w = 0; w < wave; ++w) carry += wtot[w];
-      int32_t* out = M.map + (size_t)(r0 + rl) * M.n_x0 + c0;
+      gptr<int> out = G.map + (size_t)(r0 + rl) * M.n_x0 + c0;
       for (int x0 = xs; x0 < xe; x0 += kWave) {
         const int x = x0 + lane;
         const int v = x < xe ? Drow[x] : 0;
         const int s = wave_incl_scan(v) + carry;
         if (x < xe) {
-          if (accumulate) {
-            if (s) atomicAdd(&out[x], s);
+          if (atomic) {
+            if (s) __hip_atomic_fetch_add(out + x, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           } else {
             out[x] = s;
           }
@@ -367,6 +415,7 @@ __global__ void __launch_bounds__(THREADS) k_queue(MapArgs M0, const MapArgs* __
                                                   const Unit* __restrict__ units, int n_units, int* head) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_item;
+  int loaded = -1;  // map whose A table is in LDS
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(head, 1);
     __syncthreads();
@@ -377,10 +426,11 @@ __global__ void __launch_bounds__(THREADS) k_queue(MapArgs M0, const MapArgs* __
     const int mi = u.x & ~kUnitAtomic;
     if (maps) {
       const MapArgs M = maps[mi];
-      tile_body<THREADS, ALDS>(M, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, smem);
+      tile_body<THREADS, ALDS>(M, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem);
     } else {
-      tile_body<THREADS, ALDS>(M0, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, smem);
+      tile_body<THREADS, ALDS>(M0, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem);
     }
+    loaded = mi;
     __syncthreads();
   }
 }
@@ -405,47 +455,109 @@ __global__ void k_prologue(MapArgs M0, const MapArgs* __restrict__ maps, int n_m
   }
 }
 
-// Rank structure of the windowed mode and bad-peak counting: one thread per
-// (FFT, 32-bin word).
-__device__ void prepare_one(const MapArgs& M, long long t) {
-  const int i = (int)(t / M.n_words);
-  const int w = (int)(t - (long long)i * M.n_words);
-  const int lo = min(max(M.row_ptr[i], 0), M.n_peaks);
-  const int hi = min(max(M.row_ptr[i + 1], lo), M.n_peaks);
+// Rank structure of the windowed mode and bad-peak counting, one wavefront
+// per FFT: the FFT's peaks (lanes, coalesced) add into per-word counts and OR
+// their bits into per-word masks in LDS; an exclusive scan of the counts
+// gives the peaks below each word.  Entry w of FFT i is stored at
+// rank[w * n_fft + i] as (mask << 32 | peaks below), so that the kernel's
+// lanes (consecutive FFTs) read it coalesced.  Maps with more words than the
+// LDS holds take the per-(FFT, word) binary search instead.
+constexpr int kPrepWaves = 8;
+constexpr int kPrepMaxWords = 512;
+
+__device__ void prepare_fft_lds(const MapArgs& M, int i, int lane, unsigned* cnt, unsigned* msk) {
+  const GMap G(M);
+  gptr<unsigned long long> rank = (gptr<unsigned long long>)M.rank;
+  const int lo = min(max(G.row_ptr[i], 0), M.n_peaks);
+  const int hi = min(max(G.row_ptr[i + 1], lo), M.n_peaks);
+  for (int w = lane; w < M.n_words; w += kWave) {
+    cnt[w] = 0;
+    msk[w] = 0;
+  }
+  wave_sync_lds();
+  unsigned long long bad = 0;
+  for (int p = lo + lane; p < hi; p += kWave) {
+    const int j = G.bin[p];
+    const int jm = p > lo ? G.bin[p - 1] : INT_MIN;
+    if (j <= jm) ++bad;  // not ascending
+    if (j < 0 || j >= M.n_f) {
+      ++bad;
+    } else {
+      atomicAdd(&cnt[j >> 5], 1u);
+      atomicOr(&msk[j >> 5], 1u << (j & 31));
+    }
+  }
+  wave_sync_lds();
+  // negative bins sit before word 0: they shift every word's position
+  int neg = 0;
+  for (int p = lo + lane; p < hi; p += kWave) neg += G.bin[p] < 0;
+  neg = wave_incl_scan(neg);
+  unsigned carry = (unsigned)__builtin_amdgcn_readlane(neg, 63);
+  for (int w0 = 0; w0 < M.n_words; w0 += kWave) {
+    const int w = w0 + lane;
+    const unsigned c = w < M.n_words ? cnt[w] : 0u;
+    const unsigned incl = (unsigned)wave_incl_scan((int)c) + carry;
+    if (w < M.n_words) rank[(size_t)w * M.n_fft + i] = ((unsigned long long)msk[w] << 32) | (incl - c);
+    carry = (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
+  }
+  bad = (unsigned long long)wave_incl_scan((int)bad);
+  if (lane == 63 && bad) atomicAdd(M.err, bad);
+  wave_sync_lds();
+}
+
+// Fallback for very wide bands: one thread per (FFT, word), binary search in
+// the FFT's bins.
+__device__ void prepare_word(const MapArgs& M, long long t) {
+  const GMap G(M);
+  const int i = (int)(t % M.n_fft);
+  const int w = (int)(t / M.n_fft);
+  const int lo = min(max(G.row_ptr[i], 0), M.n_peaks);
+  const int hi = min(max(G.row_ptr[i + 1], lo), M.n_peaks);
   const int key = w * 32;
   int a = lo, b = hi;
   while (a < b) {
     const int m = (a + b) >> 1;
-    if (M.bin[m] < key) a = m + 1; else b = m;
+    if (G.bin[m] < key) a = m + 1; else b = m;
   }
   unsigned mask = 0;
   unsigned long long bad = 0;
   int q = a;
   for (; q < hi; ++q) {
-    const int j = M.bin[q];
+    const int j = G.bin[q];
     if (j >= key + 32) break;
-    if (j < M.n_f) mask |= 1u << (j - key); else ++bad;
-    if (q > lo && M.bin[q - 1] >= j) ++bad;
+    if (j < M.n_f) mask |= 1u << (j & 31); else ++bad;
+    if (q > lo && G.bin[q - 1] >= j) ++bad;
   }
   if (w == 0) bad += (unsigned long long)(a - lo);
   if (w == M.n_words - 1) bad += (unsigned long long)(hi - q);
-  M.rank[(size_t)i * M.n_words + w] = make_uint2((unsigned)(a - lo), mask);
+  ((gptr<unsigned long long>)M.rank)[(size_t)w * M.n_fft + i] = ((unsigned long long)mask << 32) | (unsigned)(a - lo);
   if (bad) atomicAdd(M.err, bad);
 }
 
-__global__ void k_prepare(MapArgs M) {
-  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < (long long)M.n_fft * M.n_words) prepare_one(M, t);
+__device__ void prepare_map(const MapArgs& M, unsigned* lds) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (M.n_words <= kPrepMaxWords) {
+    unsigned* cnt = lds + wave * 2 * kPrepMaxWords;
+    for (int i = blockIdx.x * kPrepWaves + wave; i < M.n_fft; i += gridDim.x * kPrepWaves)
+      prepare_fft_lds(M, i, lane, cnt, cnt + kPrepMaxWords);
+  } else {
+    const long long n = (long long)M.n_fft * M.n_words;
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
+      prepare_word(M, t);
+  }
+}
+
+__global__ void __launch_bounds__(kPrepWaves * 64) k_prepare(MapArgs M) {
+  __shared__ unsigned lds[kPrepWaves * 2 * kPrepMaxWords];
+  prepare_map(M, lds);
 }
 
 // All windowed maps of a batch, one after the other over the whole grid.
-__global__ void k_prepare_batch(const MapArgs* __restrict__ maps, int m) {
-  const long long st = (long long)gridDim.x * blockDim.x;
+__global__ void __launch_bounds__(kPrepWaves * 64) k_prepare_batch(const MapArgs* __restrict__ maps, int m) {
+  __shared__ unsigned lds[kPrepWaves * 2 * kPrepMaxWords];
   for (int q = 0; q < m; ++q) {
     const MapArgs M = maps[q];
-    if (M.mode != kModeWindowed) continue;
-    const long long n = (long long)M.n_fft * M.n_words;
-    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += st) prepare_one(M, t);
+    if (M.mode == kModeWindowed) prepare_map(M, lds);
   }
 }
 
@@ -486,8 +598,7 @@ fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStrea
                      (const MapArgs*)nullptr, 1, (const int4*)p.dClears, n_clears, p.dHead);
   if (check_launch() != FH_OK) return FH_EDEVICE;
   if (a.mode == kModeWindowed) {
-    const long long n = (long long)a.n_fft * a.n_words;
-    hipLaunchKernelGGL(k_prepare, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_prepare, dim3(2048), dim3(kPrepWaves * 64), 0, s, a);
     if (check_launch() != FH_OK) return FH_EDEVICE;
   }
   const int th = p.tile.threads;
@@ -614,7 +725,8 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
   if (ok) {
     hipLaunchKernelGGL(k_prologue, dim3((unsigned)std::max(1, std::min(b->n_clears, 1024))), dim3(256), 0, b->cap,
                        none, (const MapArgs*)b->d_maps, m, (const int4*)b->d_clears, b->n_clears, b->d_head);
-    if (any_windowed) hipLaunchKernelGGL(k_prepare_batch, dim3(2048), dim3(256), 0, b->cap, b->d_maps, m);
+    if (any_windowed)
+      hipLaunchKernelGGL(k_prepare_batch, dim3(2048), dim3(kPrepWaves * 64), 0, b->cap, b->d_maps, m);
     hipLaunchKernelGGL((k_queue<256, true>), dim3(b->grid), dim3(256), lds, b->cap, none, (const MapArgs*)b->d_maps,
                        (const Unit*)b->d_queue, b->n_queue, b->d_head);
     ok = hipStreamEndCapture(b->cap, &b->graph) == hipSuccess;

@@ -13,6 +13,7 @@ from typing import Dict, List, Optional
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(_PKG, "tune_gfx950.json")
+CACHE_OUT = os.environ.get("FH_TUNE_OUT", CACHE)  # where autotune() writes
 _cache: Optional[Dict[str, dict]] = None
 
 
@@ -50,12 +51,14 @@ def candidates(n_x0: int, n_k: int, n_fft: int) -> List[dict]:
                     continue
                 out.append(dict(mode=1, rows=rows, cols=n_x0, threads=256, tsplit=ts))
     if n_x0 > 1024:
-        for cols in (4096, 8192, 12288, 16384, 24576, 32768):
-            if cols > n_x0 * 2:
+        for ntx in (1, 2, 3, 4, 6, 8, 12):
+            cols = (n_x0 + ntx - 1) // ntx
+            if cols > 40000:
                 continue
             for rows in (1, 2):
-                for th in (256, 512):
-                    out.append(dict(mode=2, rows=rows, cols=min(cols, n_x0), threads=th, tsplit=1))
+                for th in (256, 512, 1024):
+                    for ts in (16, 64, 256):
+                        out.append(dict(mode=2, rows=rows, cols=cols, threads=th, tsplit=ts))
     return out
 
 
@@ -99,6 +102,6 @@ def autotune(spec, pm, dev, reps: int = 10, save: bool = True, verbose: bool = F
     if save:
         c = _load()
         c[key(spec, pm.n_peaks)] = entry
-        with open(CACHE, "w") as f:
+        with open(CACHE_OUT, "w") as f:
             json.dump(c, f, indent=1, sort_keys=True)
     return entry
