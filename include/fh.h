@@ -128,6 +128,47 @@ fh_status fh_plan_set_events(fh_plan_t plan, void* start, void* stop);
  * fh_hough / batch launch of this plan.  Synchronises `stream`. */
 fh_status fh_device_errors(fh_plan_t plan, void* stream, uint64_t* out);
 
+/* ---------------------------------------------------------- selection --
+ * Candidate selection of Sec. IV: the analysed part of the map (all rows,
+ * columns [col_lo, col_hi)) is divided into sq_k x sq_x0 "squares" (row
+ * boundaries floor(a * n_k / sq_k), column boundaries col_lo + floor(b * W /
+ * sq_x0), W = col_hi - col_lo).  In every square the cell with the highest
+ * count is a candidate (ties: smallest row, then smallest column), and so is
+ * the best cell at least min_dk rows away from it (same tie rule).  Each gets
+ * the critical ratio CR = (y - mu) / sigma, mu and sigma being the mean and
+ * population standard deviation of the square's counts, computed from exact
+ * integer sums Sy, Sy2 over its N cells as
+ *     mu = Sy / N,  var = Sy2 / N - mu * mu,  sigma = sqrt(var)
+ * (binary64, this order, no contraction).  Squares with sigma = 0 give no
+ * candidate.  Candidates with CR >= cr_thr are returned in square order
+ * (best before second).  x0 and k are the cell centre x0_min + (col + 0.5) dx0
+ * and k[row]; f0 = x0^(1/(1-n)) and fdot0 = -k f0^n invert the transform. */
+typedef struct {
+  int32_t sq_k, sq_x0;   /* squares along k and along x0, >= 1 */
+  int32_t min_dk;        /* row distance of a second candidate (the paper: ~3); < 1 = none */
+  int32_t col_lo, col_hi;/* analysed columns [col_lo, col_hi); col_hi <= 0 means n_x0 */
+  double cr_thr;         /* keep candidates with CR >= cr_thr */
+} fh_select_opts;
+
+typedef struct {
+  int32_t row, col;      /* cell: k row, x0 column */
+  int32_t count;         /* Hough count y */
+  int32_t square;        /* square index a * sq_x0 + b */
+  int32_t second;        /* 0: best of its square, 1: the second candidate */
+  int32_t pad;
+  double cr, mu, sigma;  /* critical ratio and the square's statistics */
+  double x0, k, f0, fdot0;
+} fh_candidate;
+
+/* Select candidates of a Hough map (DEVICE int32 [n_k][n_x0], as written by
+ * fh_hough with this plan).  Reads the map once on `stream`, copies the
+ * per-row partial sums to the host and finishes there; synchronises `stream`.
+ * Writes min(total, cap) candidates to `out` (HOST) and the total number with
+ * CR >= cr_thr to *n_out.  Errors: FH_EINVAL (NULL pointers, sq_k outside
+ * [1, n_k], sq_x0 outside [1, min(W, 256)], bad column range), FH_EDEVICE. */
+fh_status fh_select(fh_plan_t plan, const int32_t* map, const fh_select_opts* opts, fh_candidate* out, int32_t cap,
+                    int32_t* n_out, void* stream);
+
 /* ----------------------------------------------------------- batching --
  * Many maps of uneven size in one persistent launch: every tile of every map
  * goes into one work queue, longest (estimated) first, claimed by a grid of

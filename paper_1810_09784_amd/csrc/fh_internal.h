@@ -17,6 +17,7 @@ constexpr int kLdsBudget = 160 * 1024;  // gfx950 LDS per work-group
 constexpr int kMaxJTable = 1 << 24;     // largest column->bin table of the windowed mode
 constexpr int kProfileSamples = 128;    // FFT samples of a tile's cost profile
 constexpr int kUnitAtomic = 1 << 30;    // flag bit of a unit's map field: add into the map
+constexpr int kMaxSelectSegments = 256; // squares along x0 in candidate selection
 
 enum Mode : int32_t { kModeAuto = 0, kModeWhole = 1, kModeWindowed = 2 };
 
@@ -60,7 +61,7 @@ struct Plan {
   int32_t n_f = 0, n_x0 = 0, n_J = 0, n_words = 0, t_uniform = 1;
   double x0_min = 0, dx0 = 0;
   fh_tile_cfg tile{};
-  std::vector<double> A, C, T;
+  std::vector<double> A, C, T, K;
   std::vector<int32_t> J;
   std::vector<TileProfile> prof;  // per tile
   double total_cost = 0;
@@ -76,6 +77,7 @@ struct Plan {
   Unit* dUnits = nullptr;
   int4* dClears = nullptr;
   int32_t* dHead = nullptr;
+  unsigned long long* dSel = nullptr;  // [n_k][kMaxSelectSegments][3] partial sums of fh_select
   int32_t grid = 0;  // persistent work-groups of a single-map launch
   int device = 0;
   int n_cu = 256;

@@ -242,6 +242,8 @@ static void free_dev(Plan& p) {
   if (p.dUnits) (void)hipFree(p.dUnits);
   if (p.dClears) (void)hipFree(p.dClears);
   if (p.dHead) (void)hipFree(p.dHead);
+  if (p.dSel) (void)hipFree(p.dSel);
+  p.dSel = nullptr;
   p.dUnits = nullptr;
   p.dClears = nullptr;
   p.dHead = nullptr;
@@ -341,6 +343,7 @@ extern "C" fh_status fh_plan(const fh_map_desc* d, const fh_tile_cfg* cfg, fh_pl
   try {
     p.A.resize(n_f + 1);
     p.C.resize(d->n_k);
+    p.K.assign(d->k, d->k + d->n_k);
     p.T.resize(d->n_fft);
   } catch (...) {
     delete pp;
@@ -415,6 +418,7 @@ extern "C" fh_status fh_plan(const fh_map_desc* d, const fh_tile_cfg* cfg, fh_pl
   if (st == FH_OK) st = upload<Unit>(&p.dUnits, p.units.data(), p.units.size());
   if (st == FH_OK) st = upload<int4>(&p.dClears, p.clears.data(), p.clears.size());
   if (st == FH_OK) st = upload<int32_t>(&p.dHead, nullptr, 1);
+  if (st == FH_OK) st = upload<unsigned long long>(&p.dSel, nullptr, (size_t)d->n_k * kMaxSelectSegments * 3);
   if (st == FH_OK && hipMemset(p.dErr, 0, sizeof(unsigned long long)) != hipSuccess) st = FH_EDEVICE;
   if (st != FH_OK) {
     free_dev(p);

@@ -42,6 +42,21 @@ class TileCfg(C.Structure):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
+class SelectOpts(C.Structure):
+    _fields_ = [("sq_k", C.c_int32), ("sq_x0", C.c_int32), ("min_dk", C.c_int32), ("col_lo", C.c_int32),
+                ("col_hi", C.c_int32), ("cr_thr", C.c_double)]
+
+
+class Candidate(C.Structure):
+    _fields_ = [("row", C.c_int32), ("col", C.c_int32), ("count", C.c_int32), ("square", C.c_int32),
+                ("second", C.c_int32), ("pad", C.c_int32), ("cr", C.c_double), ("mu", C.c_double),
+                ("sigma", C.c_double), ("x0", C.c_double), ("k", C.c_double), ("f0", C.c_double),
+                ("fdot0", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
+
+
 class PlanInfo(C.Structure):
     _fields_ = [("n_f", C.c_int32), ("n_x0", C.c_int32), ("n_k", C.c_int32), ("n_fft", C.c_int32),
                 ("x0_min", C.c_double), ("dx0", C.c_double), ("tile", TileCfg), ("n_tiles", C.c_int64),
@@ -66,6 +81,8 @@ SIGNATURES = {
     "fh_batch_destroy": (None, [C.c_void_p]),
     "fh_hough_batched": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(Peaks), C.POINTER(C.c_void_p),
                                    C.c_void_p]),
+    "fh_select": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SelectOpts), C.c_void_p, C.c_int32,
+                            C.POINTER(C.c_int32), C.c_void_p]),
     "fh_status_str": (C.c_char_p, [C.c_int]),
     "fh_version": (C.c_char_p, []),
 }
@@ -208,6 +225,18 @@ def fh_device_errors(plan: Plan, stream=None) -> int:
     v = C.c_uint64()
     _check(lib().fh_device_errors(plan.handle, _stream(stream), C.byref(v)), "fh_device_errors")
     return int(v.value)
+
+
+def fh_select(plan: Plan, hmap, sq_k: int, sq_x0: int, min_dk: int = 3, cr_thr: float = -1e300,
+              col_lo: int = 0, col_hi: int = 0, cap: int = 100000, stream=None):
+    """Candidates of a Hough map (list of dicts, square order)."""
+    assert hmap.is_cuda and tuple(hmap.shape) == (plan.n_k, plan.n_x0) and hmap.is_contiguous()
+    opts = SelectOpts(int(sq_k), int(sq_x0), int(min_dk), int(col_lo), int(col_hi), float(cr_thr))
+    buf = (Candidate * max(1, cap))()
+    n = C.c_int32()
+    _check(lib().fh_select(plan.handle, C.c_void_p(_ptr(hmap)), C.byref(opts), buf, int(cap), C.byref(n),
+                           _stream(stream)), "fh_select")
+    return [buf[i].as_dict() for i in range(min(n.value, cap))], int(n.value)
 
 
 class Batch:

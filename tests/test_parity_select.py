@@ -1,0 +1,108 @@
+"""fh_select (GPU pass + host finish) against the oracle selection run on the
+oracle's own Hough map."""
+import numpy as np
+import pytest
+
+from paper_1810_09784_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_09784_amd import fh
+    fh.lib()
+    return torch.device("cuda:0")
+
+
+def _gpu_map(spec, pm, dev, plan):
+    import torch
+    from paper_1810_09784_amd import fh
+    rp = torch.from_numpy(pm.row_ptr).to(dev)
+    bn = torch.from_numpy(pm.bin).to(dev)
+    return fh.fh_hough(plan, rp, bn)
+
+
+def _compare(got, ref):
+    assert len(got) == len(ref), (len(got), len(ref))
+    for g, r in zip(got, ref):
+        for key in ("row", "col", "count", "square", "second"):
+            assert g[key] == r[key], (key, g, r)
+        for key in ("cr", "mu", "sigma", "x0", "k", "f0", "fdot0"):
+            assert g[key] == r[key] or (np.isnan(g[key]) and np.isnan(r[key])), (key, g[key], r[key])
+
+
+@pytest.mark.parametrize("sq,min_dk,thr,cols", [((5, 5), 3, -1e300, (0, 0)), ((8, 3), 3, 2.0, (0, 0)),
+                                                ((1, 1), 0, -1e300, (0, 0)), ((4, 6), 5, 0.0, (30, 300))])
+def test_select_small_map(dev, oracle, sq, min_dk, thr, cols):
+    from paper_1810_09784_amd import fh
+    from oracle import select as OS
+    spec = S.cfg_single_small()
+    pm = S.make_peakmap(spec)
+    plan = fh.Plan.from_spec(spec)
+    H = _gpu_map(spec, pm, dev, plan)
+    d = oracle.Desc.from_spec(spec)
+    ref_map = oracle.hough(d, pm.row_ptr, pm.bin)
+    assert np.array_equal(H.cpu().numpy(), ref_map)
+    got, n = fh.fh_select(plan, H, sq[0], sq[1], min_dk, thr, col_lo=cols[0], col_hi=cols[1])
+    nf, x0m, dx, nx = oracle.grid(d)
+    ref = OS.select(ref_map, spec.k, x0m, dx, spec.n, sq[0], sq[1], min_dk, thr, cols[0], cols[1])
+    assert n == len(ref)
+    _compare(got, ref)
+    if sq == (5, 5) and thr < 0:
+        best = max(got, key=lambda c: c["cr"])  # the injection: k row 64, f0 = 580 Hz
+        assert best["row"] == 64 and abs(best["f0"] - 580.0) < 0.5
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_select_random_maps_with_ties(dev, oracle, seed):
+    from paper_1810_09784_amd import fh
+    from oracle import select as OS
+    rng = np.random.default_rng(300 + seed)
+    spec = S.cfg_tiny(rng, n_fft=int(rng.integers(20, 200)), n_f=int(rng.integers(20, 120)),
+                      n_k=int(rng.integers(8, 60)), n=float(rng.choice([2.0, 3.0, 5.0])), tfft=2.0,
+                      f_min=float(rng.integers(100, 800)), kscale=0.05)
+    pm = S.random_peakmap(rng, spec.n_fft, spec.n_f, 0.05)  # small counts: many ties
+    plan = fh.Plan.from_spec(spec)
+    H = _gpu_map(spec, pm, dev, plan)
+    d = oracle.Desc.from_spec(spec)
+    ref_map = oracle.hough(d, pm.row_ptr, pm.bin)
+    assert np.array_equal(H.cpu().numpy(), ref_map)
+    sk = int(rng.integers(1, min(8, spec.n_k) + 1))
+    sx = int(rng.integers(1, min(8, plan.n_x0) + 1))
+    got, n = fh.fh_select(plan, H, sk, sx, 3)
+    nf, x0m, dx, nx = oracle.grid(d)
+    _compare(got, OS.select(ref_map, spec.k, x0m, dx, spec.n, sk, sx, 3))
+
+
+def test_large_map_full_parity_and_select(dev, oracle):
+    # the whole 1024 x 84000 map against the oracle's, then 5 x 5 squares
+    from paper_1810_09784_amd import fh
+    from oracle import select as OS
+    spec = S.cfg_single_large()
+    pm = S.make_peakmap(spec)
+    plan = fh.Plan.from_spec(spec)
+    H = _gpu_map(spec, pm, dev, plan)
+    d = oracle.Desc.from_spec(spec)
+    ref_map = oracle.hough(d, pm.row_ptr, pm.bin)
+    got_map = H.cpu().numpy()
+    bad = np.argwhere(got_map != ref_map)
+    assert len(bad) == 0, f"{len(bad)} cells differ, first {bad[:3]}"
+    got, n = fh.fh_select(plan, H, 5, 5, 3)
+    nf, x0m, dx, nx = oracle.grid(d)
+    _compare(got, OS.select(ref_map, spec.k, x0m, dx, spec.n, 5, 5, 3))
+
+
+def test_select_rejects_bad_options(dev):
+    from paper_1810_09784_amd import fh
+    spec = S.cfg_single_small()
+    plan = fh.Plan.from_spec(spec)
+    import torch
+    H = torch.zeros((plan.n_k, plan.n_x0), dtype=torch.int32, device=dev)
+    for kw in (dict(sq_k=0, sq_x0=1), dict(sq_k=1, sq_x0=0), dict(sq_k=plan.n_k + 1, sq_x0=1),
+               dict(sq_k=1, sq_x0=1, col_lo=10, col_hi=5), dict(sq_k=1, sq_x0=300)):
+        with pytest.raises(fh.FHError):
+            fh.fh_select(plan, H, **kw)
