@@ -169,6 +169,48 @@ typedef struct {
 fh_status fh_select(fh_plan_t plan, const int32_t* map, const fh_select_opts* opts, fh_candidate* out, int32_t cap,
                     int32_t* n_out, void* stream);
 
+/* ---------------------------------------------------------- tile CNN --
+ * A learned proposer of 64 x 64 map tiles (not in the paper, whose last
+ * section only plans machine learning): tile (counts normalised by their map
+ * row's mean and standard deviation) -> 4 x [3x3 conv, zero padding, bias,
+ * ReLU] with 1 -> 16 -> 32 -> 64 -> 64 channels -> global average pool ->
+ * linear 64 -> 1 -> logistic; 60289 FP32 parameters, flat order w1 [16][9],
+ * b1, w2 [32][9*16], b2, w3 [64][9*32], b3, w4 [64][9*64], b4, w5 [64], b5,
+ * conv weight index (co, k = (dy*3 + dx)*Cin + ci).  Activations, weights and
+ * activation gradients are BF16 (round to nearest even), sums FP32 (matrix
+ * cores for conv2..4).  Tiles are DEVICE BF16 [B][64][64] (row = k, col = x0).
+ * A network object owns its parameters, Adam state and the activations of
+ * up to max_batch tiles; it is used from one stream at a time. */
+typedef struct fh_cnn_s* fh_cnn_t;
+
+fh_status fh_cnn_create(int32_t max_batch, fh_cnn_t* out);          /* parameters zero */
+void fh_cnn_destroy(fh_cnn_t net);
+int64_t fh_cnn_num_params(void);                                    /* 60289 */
+/* HOST float [n] in the flat order; resets the Adam state.  Synchronous. */
+fh_status fh_cnn_set_params(fh_cnn_t net, const float* params, int64_t n);
+/* HOST copies of the parameters and of the last backward's gradients (either may be NULL). */
+fh_status fh_cnn_get_params(fh_cnn_t net, float* params, float* grads, int64_t n);
+/* logits (DEVICE float [B], may be NULL) of B <= max_batch tiles; keeps the activations. */
+fh_status fh_cnn_forward(fh_cnn_t net, const uint16_t* tiles, int32_t B, float* logits, void* stream);
+/* Mean binary cross-entropy of the last forward against labels (DEVICE float [B], 0/1)
+ * and its gradients (replacing the previous ones); loss: DEVICE float, may be NULL. */
+fh_status fh_cnn_backward(fh_cnn_t net, const float* labels, int32_t B, float* loss, void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with learning rate lr. */
+fh_status fh_cnn_step(fh_cnn_t net, float lr, void* stream);
+/* Normalised tiles of a DEVICE int32 map [n_k][n_x0]: per-row mean and 1/std
+ * (DEVICE float [n_k] each, written) and tiles (DEVICE BF16 [n_tiles][64][64])
+ * at origins (DEVICE int32 [n_tiles][2] = (row, col)); zero outside the map. */
+fh_status fh_tiles(const int32_t* map, int32_t n_k, int32_t n_x0, const int32_t* origins, int32_t n_tiles,
+                   uint16_t* tiles, float* row_mean, float* row_istd, void* stream);
+/* Score every 64 x 64 tile of a Hough map of `plan` (tile (a, b) at row 64a,
+ * column 64b; scores: DEVICE float [ceil(n_k/64) * ceil(n_x0/64)], the
+ * logits, row-major over (a, b)) and return the n_top best tile indices
+ * (HOST int32, best first) in tile_ids.  Uses the network's activations as
+ * scratch; allocates a row-statistics buffer on first use or growth.
+ * Synchronises `stream`. */
+fh_status fh_propose(fh_cnn_t net, fh_plan_t plan, const int32_t* map, float* scores, int32_t n_top,
+                     int32_t* tile_ids, void* stream);
+
 /* ----------------------------------------------------------- batching --
  * Many maps of uneven size in one persistent launch: every tile of every map
  * goes into one work queue, longest (estimated) first, claimed by a grid of

@@ -1,0 +1,642 @@
+// Tile CNN on Hough maps: proposes the 64 x 64 tiles of a map worth the
+// plain candidate selection's attention.  Not part of the paper's method: its
+// closing section only plans machine learning for the search; here a small
+// network is trained on maps the method itself produces from synthetic
+// injections, and the plain selection stays the judge.
+//
+// Network: tile (1 channel, counts normalised per map row) -> 4 x [conv 3x3,
+// stride 1, zero padding, bias, ReLU] with 1 -> 16 -> 32 -> 64 -> 64 channels
+// -> global average pool -> linear 64 -> 1 -> logistic.  60289 parameters.
+//
+// Numerics: activations, weights and activation gradients are BF16 (round to
+// nearest even); every product sum accumulates in FP32.  conv2..conv4 and
+// their backward passes are implicit GEMMs on the BF16 matrix cores
+// (v_mfma_f32_16x16x32_bf16 / 16x16x16); conv1 (one input channel) and the
+// head are plain FP32 VALU code.  Master weights and Adam state are FP32.
+//
+// Layouts: activations NHWC [B][64][64][C] bf16; conv weights [Cout][9*Cin]
+// with k = (dy*3 + dx)*Cin + ci; flat parameter vector (FP32) in the order
+// w1, b1, w2, b2, w3, b3, w4, b4, w5, b5.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "fh_internal.h"
+
+namespace fh {
+namespace cnn {
+
+constexpr int HW = 64;           // tile side
+constexpr int NPIX = HW * HW;
+constexpr int C1 = 16, C2 = 32, C3 = 64, C4 = 64;
+constexpr int NW1 = C1 * 9, NW2 = C2 * 9 * C1, NW3 = C3 * 9 * C2, NW4 = C4 * 9 * C3;
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NW1, OFF_W2 = OFF_B1 + C1, OFF_B2 = OFF_W2 + NW2;
+constexpr int OFF_W3 = OFF_B2 + C2, OFF_B3 = OFF_W3 + NW3, OFF_W4 = OFF_B3 + C3, OFF_B4 = OFF_W4 + NW4;
+constexpr int OFF_W5 = OFF_B4 + C4, OFF_B5 = OFF_W5 + C4, NPARAM = OFF_B5 + 1;
+static_assert(NPARAM == 60289, "parameter count of the tile network");
+
+typedef unsigned short bf16_t;
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+
+__host__ __device__ inline bf16_t f2bf(float f) {
+  unsigned u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (bf16_t)(u >> 16);  // inf / nan kept
+  u += 0x7fffu + ((u >> 16) & 1u);                                  // round to nearest even
+  return (bf16_t)(u >> 16);
+}
+__host__ __device__ inline float bf2f(bf16_t h) {
+  unsigned u = (unsigned)h << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+template <int KW>
+struct Frag;
+template <>
+struct Frag<16> {
+  typedef s4 T;
+};
+template <>
+struct Frag<32> {
+  typedef s8 T;
+};
+
+template <int KW>
+__device__ __forceinline__ f4 mfma(typename Frag<KW>::T a, typename Frag<KW>::T b, f4 c) {
+  if constexpr (KW == 32)
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, a), __builtin_bit_cast(b8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------ conv (GEMM) --
+// Implicit-GEMM 3x3 convolution on the matrix cores.  One work-group = 4
+// output rows of one tile (a wavefront per row: 4 pixel tiles of 16 x all
+// output-channel tiles of 16).  Rows y0-1 .. y0+4 of the input (with the zero
+// border) and the whole weight matrix are staged in LDS.
+//   FWD:  out = bf16(relu(bias + conv(in, w)))
+//   BWD:  out = bf16(conv(in, w) * (mask > 0))   (in = dY, w = flipped w^T,
+//         mask = the forward input of the layer: the ReLU derivative)
+template <int CIN, int COUT, bool BWD>
+__global__ void __launch_bounds__(256) k_conv(const bf16_t* __restrict__ in, const bf16_t* __restrict__ w,
+                                              const float* __restrict__ bias, const bf16_t* __restrict__ mask,
+                                              bf16_t* __restrict__ out) {
+  constexpr int K = 9 * CIN;
+  constexpr int KW = (K % 32 == 0) ? 32 : 16;
+  constexpr int NCT = COUT / 16;
+  constexpr int ROWS = 6, COLS = HW + 2;
+  extern __shared__ __align__(16) unsigned char smem[];
+  bf16_t* xin = reinterpret_cast<bf16_t*>(smem);  // [ROWS][COLS][CIN]
+  bf16_t* wl = xin + ROWS * COLS * CIN;           // [COUT][K]
+  const int b = blockIdx.x / (HW / 4);
+  const int y0 = (blockIdx.x % (HW / 4)) * 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const bf16_t* inb = in + (size_t)b * NPIX * CIN;
+  // stage input rows (zero outside the tile) and weights
+  for (int e = tid; e < ROWS * COLS * CIN; e += 256) {
+    const int c = e % CIN, col = (e / CIN) % COLS, row = e / (CIN * COLS);
+    const int y = y0 - 1 + row, x = col - 1;
+    xin[e] = (y >= 0 && y < HW && x >= 0 && x < HW) ? inb[((size_t)y * HW + x) * CIN + c] : (bf16_t)0;
+  }
+  for (int e = tid; e < COUT * K; e += 256) wl[e] = w[e];
+  __syncthreads();
+  f4 acc[4][NCT];
+#pragma unroll
+  for (int pt = 0; pt < 4; ++pt)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct) acc[pt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+  const int g = lane >> 4, m = lane & 15;
+  constexpr int EL = KW / 4;  // bf16 per lane per fragment
+  for (int kc = 0; kc < K; kc += KW) {
+    const int k = kc + g * EL;
+    const int tap = k / CIN, ci = k % CIN;
+    const int dy = tap / 3, dx = tap % 3;
+    typename Frag<KW>::T bf[NCT];
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+      bf[ct] = *reinterpret_cast<const typename Frag<KW>::T*>(wl + (ct * 16 + m) * K + k);
+#pragma unroll
+    for (int pt = 0; pt < 4; ++pt) {
+      const int x = pt * 16 + m;
+      const typename Frag<KW>::T af =
+          *reinterpret_cast<const typename Frag<KW>::T*>(xin + ((wave + dy) * COLS + (x + dx)) * CIN + ci);
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct) acc[pt][ct] = mfma<KW>(af, bf[ct], acc[pt][ct]);
+    }
+  }
+  const int y = y0 + wave;
+  bf16_t* ob = out + (size_t)b * NPIX * COUT;
+#pragma unroll
+  for (int pt = 0; pt < 4; ++pt)
+#pragma unroll
+    for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int x = pt * 16 + g * 4 + i;
+        const int co = ct * 16 + m;
+        const size_t o = ((size_t)y * HW + x) * COUT + co;
+        float v = acc[pt][ct][i];
+        if (BWD) {
+          v = bf2f(mask[(size_t)b * NPIX * COUT + o]) > 0.f ? v : 0.f;
+        } else {
+          v = fmaxf(v + bias[co], 0.f);
+        }
+        ob[o] = f2bf(v);
+      }
+}
+
+template <int CIN, int COUT>
+constexpr int conv_lds() {
+  return (6 * (HW + 2) * CIN + COUT * 9 * CIN) * 2;
+}
+
+// Weight gradient of a 3x3 convolution on the matrix cores: dW[co][k] +=
+// sum over pixels of dY[p][co] * in_col[p][k].  One work-group per tile; per
+// output row it stages dY transposed ([co][x]) and three dx-shifted,
+// transposed copies of input rows y-1..y+1 ([dx][dy][ci][x]) so that every
+// fragment is one aligned LDS read; the tile's partial sums are added into
+// dW (and dbias) with atomics at the end.
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ in, const bf16_t* __restrict__ dy,
+                                                    float* __restrict__ dw, float* __restrict__ db) {
+  constexpr int K = 9 * CIN;
+  constexpr int MT = COUT / 16, NT = K / 16, TILES = MT * NT;
+  constexpr int TPW = (TILES + 3) / 4;  // tiles per wavefront
+  extern __shared__ __align__(16) unsigned char smem[];
+  bf16_t* dyT = reinterpret_cast<bf16_t*>(smem);  // [COUT][HW]
+  bf16_t* xT = dyT + COUT * HW;                    // [3 dx][3 dy][CIN][HW]
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, m = lane & 15;
+  const bf16_t* inb = in + (size_t)b * NPIX * CIN;
+  const bf16_t* dyb = dy + (size_t)b * NPIX * COUT;
+  f4 acc[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;  // dbias partial: thread tid < COUT
+  for (int y = 0; y < HW; ++y) {
+    __syncthreads();
+    for (int e = tid; e < COUT * HW; e += 256) {
+      const int co = e % COUT, x = e / COUT;
+      dyT[co * HW + x] = dyb[((size_t)y * HW + x) * COUT + co];
+    }
+    for (int e = tid; e < 9 * CIN * HW; e += 256) {
+      const int ci = e % CIN, x = (e / CIN) % HW, t = e / (CIN * HW);
+      const int ddx = t % 3, ddy = t / 3;
+      const int yy = y + ddy - 1, xx = x + ddx - 1;
+      xT[((ddx * 3 + ddy) * CIN + ci) * HW + x] =
+          (yy >= 0 && yy < HW && xx >= 0 && xx < HW) ? inb[((size_t)yy * HW + xx) * CIN + ci] : (bf16_t)0;
+    }
+    __syncthreads();
+    if (tid < COUT)
+      for (int x = 0; x < HW; ++x) bsum += bf2f(dyT[tid * HW + x]);
+    for (int pc = 0; pc < HW; pc += 32) {  // 32 pixels per MFMA step
+      const int x = pc + g * 8;
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int tile = wave * TPW + t;
+        if (tile < TILES) {
+          const int mt = tile / NT, nt = tile % NT;
+          const int co = mt * 16 + m;
+          const int k = nt * 16 + m;
+          const int tap = k / CIN, ci = k % CIN;
+          const int ddy = tap / 3, ddx = tap % 3;
+          const s8 a = *reinterpret_cast<const s8*>(dyT + co * HW + x);
+          const s8 bb = *reinterpret_cast<const s8*>(xT + ((ddx * 3 + ddy) * CIN + ci) * HW + x);
+          acc[t] = mfma<32>(a, bb, acc[t]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    const int tile = wave * TPW + t;
+    if (tile < TILES) {
+      const int mt = tile / NT, nt = tile % NT;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int co = mt * 16 + g * 4 + i;
+        const int k = nt * 16 + m;
+        atomicAdd(&dw[co * K + k], acc[t][i]);
+      }
+    }
+  }
+  if (tid < COUT) atomicAdd(&db[tid], bsum);
+}
+
+template <int CIN, int COUT>
+constexpr int wgrad_lds() {
+  return (COUT * HW + 9 * CIN * HW) * 2;
+}
+
+// ---------------------------------------------------------- conv1 (VALU) --
+__global__ void __launch_bounds__(256) k_conv1_fwd(const bf16_t* __restrict__ in, const float* __restrict__ w1,
+                                                   const float* __restrict__ b1, bf16_t* __restrict__ out, int B) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // one pixel
+  if (t >= (long long)B * NPIX) return;
+  const int b = (int)(t / NPIX), p = (int)(t % NPIX), y = p / HW, x = p % HW;
+  float v[9];
+  for (int tap = 0; tap < 9; ++tap) {
+    const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+    v[tap] = (yy >= 0 && yy < HW && xx >= 0 && xx < HW) ? bf2f(in[(size_t)b * NPIX + yy * HW + xx]) : 0.f;
+  }
+  for (int co = 0; co < C1; ++co) {
+    float s = 0.f;
+    for (int tap = 0; tap < 9; ++tap) s += bf2f(f2bf(w1[co * 9 + tap])) * v[tap];
+    out[(size_t)t * C1 + co] = f2bf(fmaxf(s + b1[co], 0.f));
+  }
+}
+
+// dW1[co][tap] = sum_p dY1[p][co] * in[p + tap]; one work-group per tile.
+__global__ void __launch_bounds__(256) k_conv1_wgrad(const bf16_t* __restrict__ in, const bf16_t* __restrict__ dy,
+                                                     float* __restrict__ dw, float* __restrict__ db) {
+  __shared__ float part[256][C1 + 1];
+  const int b = blockIdx.x;
+  float acc[C1 * 9 + C1];
+  for (int e = 0; e < C1 * 9 + C1; ++e) acc[e] = 0.f;
+  for (int p = threadIdx.x; p < NPIX; p += 256) {
+    const int y = p / HW, x = p % HW;
+    float v[9];
+    for (int tap = 0; tap < 9; ++tap) {
+      const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+      v[tap] = (yy >= 0 && yy < HW && xx >= 0 && xx < HW) ? bf2f(in[(size_t)b * NPIX + yy * HW + xx]) : 0.f;
+    }
+    for (int co = 0; co < C1; ++co) {
+      const float d = bf2f(dy[((size_t)b * NPIX + p) * C1 + co]);
+      for (int tap = 0; tap < 9; ++tap) acc[co * 9 + tap] += d * v[tap];
+      acc[C1 * 9 + co] += d;
+    }
+  }
+  for (int e = 0; e < C1 * 9 + C1; e += C1) {
+    for (int q = 0; q < C1; ++q) part[threadIdx.x][q] = acc[e + q];
+    __syncthreads();
+    if (threadIdx.x < C1) {
+      float s = 0.f;
+      for (int r = 0; r < 256; ++r) s += part[r][threadIdx.x];
+      const int idx = e + threadIdx.x;
+      if (idx < C1 * 9) atomicAdd(&dw[idx], s); else atomicAdd(&db[idx - C1 * 9], s);
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ head --
+// feat[b][c] = mean over pixels of act4; logit = feat . w5 + b5.
+__global__ void __launch_bounds__(256) k_head_fwd(const bf16_t* __restrict__ act4, const float* __restrict__ w5,
+                                                  const float* __restrict__ b5, float* __restrict__ feat,
+                                                  float* __restrict__ logit) {
+  __shared__ float part[4][C4];
+  const int b = blockIdx.x, c = threadIdx.x & 63, q = threadIdx.x >> 6;
+  float s = 0.f;
+  for (int p = q; p < NPIX; p += 4) s += bf2f(act4[((size_t)b * NPIX + p) * C4 + c]);
+  part[q][c] = s;
+  __syncthreads();
+  if (threadIdx.x < C4) {
+    const float f = (part[0][c] + part[1][c] + part[2][c] + part[3][c]) * (1.0f / NPIX);
+    feat[b * C4 + c] = f;
+    part[0][c] = f * w5[c];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float z = b5[0];
+    for (int e = 0; e < C4; ++e) z += part[0][e];
+    logit[b] = z;
+  }
+}
+
+// Binary cross-entropy of the batch (mean) and its gradient back to act4.
+__global__ void __launch_bounds__(256) k_head_bwd(const bf16_t* __restrict__ act4, const float* __restrict__ feat,
+                                                  const float* __restrict__ logit, const float* __restrict__ label,
+                                                  const float* __restrict__ w5, float* __restrict__ dw5,
+                                                  float* __restrict__ db5, float* __restrict__ loss,
+                                                  bf16_t* __restrict__ dact4, int B) {
+  const int b = blockIdx.x;
+  const float z = logit[b], yv = label[b];
+  const float pr = 1.f / (1.f + expf(-z));
+  const float dz = (pr - yv) / (float)B;
+  if (threadIdx.x < C4) atomicAdd(&dw5[threadIdx.x], dz * feat[b * C4 + threadIdx.x]);
+  if (threadIdx.x == 0) {
+    atomicAdd(db5, dz);
+    // log(1 + e^-|z|) form of -[y log p + (1 - y) log(1 - p)]
+    const float l = fmaxf(z, 0.f) - z * yv + log1pf(expf(-fabsf(z)));
+    atomicAdd(loss, l / (float)B);
+  }
+  for (int e = threadIdx.x; e < NPIX * C4; e += 256) {
+    const int c = e % C4;
+    const size_t o = (size_t)b * NPIX * C4 + e;
+    const float g = bf2f(act4[o]) > 0.f ? dz * w5[c] * (1.0f / NPIX) : 0.f;
+    dact4[o] = f2bf(g);
+  }
+}
+
+// ------------------------------------------------------------- optimiser --
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
+                       float* __restrict__ m2, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float a = b1 * m1[i] + (1.f - b1) * gi;
+  const float v = b2 * m2[i] + (1.f - b2) * gi * gi;
+  m1[i] = a;
+  m2[i] = v;
+  p[i] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
+}
+
+// BF16 weight copies for the matrix cores: w (forward, [Cout][9 Cin]) and the
+// flipped transpose wt ([Cin][9 Cout], k' = ((2-dy)*3 + (2-dx))*Cout + co)
+// used by the data gradient.
+__global__ void k_pack(const float* __restrict__ src, int cin, int cout, bf16_t* __restrict__ w,
+                       bf16_t* __restrict__ wt) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= cout * 9 * cin) return;
+  const int co = e / (9 * cin), k = e % (9 * cin), tap = k / cin, ci = k % cin;
+  const bf16_t h = f2bf(src[e]);
+  w[e] = h;
+  if (wt) wt[(size_t)ci * 9 * cout + (8 - tap) * cout + co] = h;
+}
+
+// ---------------------------------------------------------- tile inputs --
+// Per map row: mean and 1/std of the counts over the whole row (exact int64
+// sums, FP64 statistics).
+__global__ void __launch_bounds__(256) k_row_stats(const int32_t* __restrict__ map, int n_x0, float* __restrict__ mean,
+                                                   float* __restrict__ istd) {
+  __shared__ long long s1[256], s2[256];
+  const int r = blockIdx.x;
+  long long a = 0, q = 0;
+  for (int c = threadIdx.x; c < n_x0; c += 256) {
+    const long long v = map[(size_t)r * n_x0 + c];
+    a += v;
+    q += v * v;
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = q;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      s1[threadIdx.x] += s1[threadIdx.x + o];
+      s2[threadIdx.x] += s2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mu = (double)s1[0] / n_x0;
+    const double var = (double)s2[0] / n_x0 - mu * mu;
+    mean[r] = (float)mu;
+    istd[r] = var > 0 ? (float)(1.0 / sqrt(var)) : 0.f;
+  }
+}
+
+// tiles[t][y][x] = bf16((map[r0+y][c0+x] - mean[r0+y]) * istd[r0+y]), zero outside the map
+__global__ void __launch_bounds__(256) k_gather(const int32_t* __restrict__ map, int n_k, int n_x0,
+                                                const float* __restrict__ mean, const float* __restrict__ istd,
+                                                const int2* __restrict__ origin, bf16_t* __restrict__ tiles) {
+  const int t = blockIdx.x;
+  const int2 o = origin[t];
+  for (int e = threadIdx.x; e < NPIX; e += 256) {
+    const int y = e / HW, x = e % HW, r = o.x + y, c = o.y + x;
+    float v = 0.f;
+    if (r >= 0 && r < n_k && c >= 0 && c < n_x0) v = ((float)map[(size_t)r * n_x0 + c] - mean[r]) * istd[r];
+    tiles[(size_t)t * NPIX + e] = f2bf(v);
+  }
+}
+
+}  // namespace cnn
+}  // namespace fh
+
+// ===================================================================== ABI ==
+using namespace fh::cnn;
+
+struct fh_cnn_s {
+  int max_batch = 0;
+  float *params = nullptr, *grads = nullptr, *m1 = nullptr, *m2 = nullptr;
+  bf16_t *w2 = nullptr, *w3 = nullptr, *w4 = nullptr, *w2t = nullptr, *w3t = nullptr, *w4t = nullptr;
+  bf16_t *x = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *a4 = nullptr;  // activations
+  bf16_t *d1 = nullptr, *d2 = nullptr, *d3 = nullptr, *d4 = nullptr;               // activation gradients
+  float *feat = nullptr, *logit = nullptr, *loss = nullptr;
+  float *row_mean = nullptr, *row_istd = nullptr;
+  int row_cap = 0;
+  int2* origins = nullptr;
+  int steps = 0;
+  int last_batch = 0;
+};
+
+namespace {
+
+template <typename T>
+bool dalloc(T** p, size_t n) {
+  return hipMalloc((void**)p, sizeof(T) * (n ? n : 1)) == hipSuccess;
+}
+
+void cnn_free(fh_cnn_s* c) {
+  if (!c) return;
+  void* ptrs[] = {c->params, c->grads, c->m1,  c->m2,   c->w2,    c->w3,    c->w4, c->w2t, c->w3t, c->w4t, c->x,
+                  c->a1,     c->a2,    c->a3,  c->a4,   c->d1,    c->d2,    c->d3, c->d4,  c->feat, c->logit,
+                  c->loss,   c->row_mean, c->row_istd, c->origins};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete c;
+}
+
+template <int CIN, int COUT, bool BWD>
+fh_status launch_conv(const bf16_t* in, const bf16_t* w, const float* bias, const bf16_t* mask, bf16_t* out, int B,
+                      hipStream_t s) {
+  constexpr int lds = conv_lds<CIN, COUT>();
+  (void)hipFuncSetAttribute((const void*)k_conv<CIN, COUT, BWD>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  hipLaunchKernelGGL((k_conv<CIN, COUT, BWD>), dim3(B * (HW / 4)), dim3(256), lds, s, in, w, bias, mask, out);
+  return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
+}
+
+template <int CIN, int COUT>
+fh_status launch_wgrad(const bf16_t* in, const bf16_t* dy, float* dw, float* db, int B, hipStream_t s) {
+  constexpr int lds = wgrad_lds<CIN, COUT>();
+  (void)hipFuncSetAttribute((const void*)k_conv_wgrad<CIN, COUT>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  hipLaunchKernelGGL((k_conv_wgrad<CIN, COUT>), dim3(B), dim3(256), lds, s, in, dy, dw, db);
+  return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
+}
+
+fh_status pack(fh_cnn_s* c, hipStream_t s) {
+  const struct {
+    int off, cin, cout;
+    bf16_t *w, *wt;
+  } L[3] = {{OFF_W2, C1, C2, c->w2, c->w2t}, {OFF_W3, C2, C3, c->w3, c->w3t}, {OFF_W4, C3, C4, c->w4, c->w4t}};
+  for (const auto& l : L) {
+    const int n = l.cout * 9 * l.cin;
+    hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, s, c->params + l.off, l.cin, l.cout, l.w, l.wt);
+  }
+  return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" fh_status fh_cnn_create(int32_t max_batch, fh_cnn_t* out) {
+  if (max_batch < 1 || max_batch > 65536 || !out) return FH_EINVAL;
+  fh_cnn_s* c = new (std::nothrow) fh_cnn_s();
+  if (!c) return FH_ENOMEM;
+  c->max_batch = max_batch;
+  const size_t P = (size_t)max_batch * NPIX;
+  bool ok = dalloc(&c->params, NPARAM) && dalloc(&c->grads, NPARAM) && dalloc(&c->m1, NPARAM) &&
+            dalloc(&c->m2, NPARAM) && dalloc(&c->w2, NW2) && dalloc(&c->w3, NW3) && dalloc(&c->w4, NW4) &&
+            dalloc(&c->w2t, NW2) && dalloc(&c->w3t, NW3) && dalloc(&c->w4t, NW4) && dalloc(&c->x, P) &&
+            dalloc(&c->a1, P * C1) && dalloc(&c->a2, P * C2) && dalloc(&c->a3, P * C3) && dalloc(&c->a4, P * C4) &&
+            dalloc(&c->d1, P * C1) && dalloc(&c->d2, P * C2) && dalloc(&c->d3, P * C3) && dalloc(&c->d4, P * C4) &&
+            dalloc(&c->feat, (size_t)max_batch * C4) && dalloc(&c->logit, max_batch) && dalloc(&c->loss, 1) &&
+            dalloc(&c->origins, max_batch);
+  if (!ok) {
+    cnn_free(c);
+    return FH_ENOMEM;
+  }
+  if (hipMemset(c->params, 0, NPARAM * 4) != hipSuccess || hipMemset(c->m1, 0, NPARAM * 4) != hipSuccess ||
+      hipMemset(c->m2, 0, NPARAM * 4) != hipSuccess || hipMemset(c->grads, 0, NPARAM * 4) != hipSuccess) {
+    cnn_free(c);
+    return FH_EDEVICE;
+  }
+  *out = reinterpret_cast<fh_cnn_t>(c);
+  return FH_OK;
+}
+
+extern "C" void fh_cnn_destroy(fh_cnn_t h) { cnn_free(reinterpret_cast<fh_cnn_s*>(h)); }
+
+extern "C" int64_t fh_cnn_num_params(void) { return NPARAM; }
+
+extern "C" fh_status fh_cnn_set_params(fh_cnn_t h, const float* host, int64_t n) {
+  if (!h || !host || n != NPARAM) return FH_EINVAL;
+  fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);
+  if (hipMemcpy(c->params, host, NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess) return FH_EDEVICE;
+  if (hipMemset(c->m1, 0, NPARAM * 4) != hipSuccess || hipMemset(c->m2, 0, NPARAM * 4) != hipSuccess)
+    return FH_EDEVICE;
+  c->steps = 0;
+  if (pack(c, nullptr) != FH_OK || hipDeviceSynchronize() != hipSuccess) return FH_EDEVICE;
+  return FH_OK;
+}
+
+extern "C" fh_status fh_cnn_get_params(fh_cnn_t h, float* host, float* grads_host, int64_t n) {
+  if (!h || n != NPARAM) return FH_EINVAL;
+  fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);
+  if (hipDeviceSynchronize() != hipSuccess) return FH_EDEVICE;
+  if (host && hipMemcpy(host, c->params, NPARAM * 4, hipMemcpyDeviceToHost) != hipSuccess) return FH_EDEVICE;
+  if (grads_host && hipMemcpy(grads_host, c->grads, NPARAM * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return FH_EDEVICE;
+  return FH_OK;
+}
+
+extern "C" fh_status fh_cnn_forward(fh_cnn_t h, const uint16_t* tiles, int32_t B, float* logits, void* stream) {
+  if (!h || !tiles || B < 1) return FH_EINVAL;
+  fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);
+  if (B > c->max_batch) return FH_ERANGE;
+  hipStream_t s = (hipStream_t)stream;
+  if (tiles != c->x &&
+      hipMemcpyAsync(c->x, tiles, (size_t)B * NPIX * 2, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return FH_EDEVICE;
+  const long long npx = (long long)B * NPIX;
+  hipLaunchKernelGGL(k_conv1_fwd, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, c->x, c->params + OFF_W1,
+                     c->params + OFF_B1, c->a1, B);
+  fh_status st = launch_conv<C1, C2, false>(c->a1, c->w2, c->params + OFF_B2, nullptr, c->a2, B, s);
+  if (st == FH_OK) st = launch_conv<C2, C3, false>(c->a2, c->w3, c->params + OFF_B3, nullptr, c->a3, B, s);
+  if (st == FH_OK) st = launch_conv<C3, C4, false>(c->a3, c->w4, c->params + OFF_B4, nullptr, c->a4, B, s);
+  if (st != FH_OK) return st;
+  hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(256), 0, s, c->a4, c->params + OFF_W5, c->params + OFF_B5, c->feat,
+                     c->logit);
+  if (logits && hipMemcpyAsync(logits, c->logit, (size_t)B * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return FH_EDEVICE;
+  c->last_batch = B;
+  return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
+}
+
+extern "C" fh_status fh_cnn_backward(fh_cnn_t h, const float* labels, int32_t B, float* loss, void* stream) {
+  if (!h || !labels || B < 1) return FH_EINVAL;
+  fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);
+  if (B != c->last_batch) return FH_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemsetAsync(c->grads, 0, NPARAM * 4, s) != hipSuccess || hipMemsetAsync(c->loss, 0, 4, s) != hipSuccess)
+    return FH_EDEVICE;
+  hipLaunchKernelGGL(k_head_bwd, dim3(B), dim3(256), 0, s, c->a4, c->feat, c->logit, labels, c->params + OFF_W5,
+                     c->grads + OFF_W5, c->grads + OFF_B5, c->loss, c->d4, B);
+  fh_status st = launch_wgrad<C3, C4>(c->a3, c->d4, c->grads + OFF_W4, c->grads + OFF_B4, B, s);
+  if (st == FH_OK) st = launch_conv<C4, C3, true>(c->d4, c->w4t, nullptr, c->a3, c->d3, B, s);
+  if (st == FH_OK) st = launch_wgrad<C2, C3>(c->a2, c->d3, c->grads + OFF_W3, c->grads + OFF_B3, B, s);
+  if (st == FH_OK) st = launch_conv<C3, C2, true>(c->d3, c->w3t, nullptr, c->a2, c->d2, B, s);
+  if (st == FH_OK) st = launch_wgrad<C1, C2>(c->a1, c->d2, c->grads + OFF_W2, c->grads + OFF_B2, B, s);
+  if (st == FH_OK) st = launch_conv<C2, C1, true>(c->d2, c->w2t, nullptr, c->a1, c->d1, B, s);
+  if (st != FH_OK) return st;
+  hipLaunchKernelGGL(k_conv1_wgrad, dim3(B), dim3(256), 0, s, c->x, c->d1, c->grads + OFF_W1, c->grads + OFF_B1);
+  if (loss && hipMemcpyAsync(loss, c->loss, 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return FH_EDEVICE;
+  return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
+}
+
+extern "C" fh_status fh_cnn_step(fh_cnn_t h, float lr, void* stream) {
+  if (!h || !(lr >= 0.f)) return FH_EINVAL;
+  fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);
+  hipStream_t s = (hipStream_t)stream;
+  c->steps += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.f - std::pow(b1, (float)c->steps), c2 = 1.f - std::pow(b2, (float)c->steps);
+  hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, s, c->params, c->grads, c->m1, c->m2, NPARAM,
+                     lr, b1, b2, 1e-8f, c1, c2);
+  return pack(c, s);
+}
+
+extern "C" fh_status fh_tiles(const int32_t* map, int32_t n_k, int32_t n_x0, const int32_t* origins, int32_t n_tiles,
+                              uint16_t* tiles, float* row_mean, float* row_istd, void* stream) {
+  if (!map || !origins || !tiles || !row_mean || !row_istd || n_k < 1 || n_x0 < 1 || n_tiles < 0) return FH_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_row_stats, dim3(n_k), dim3(256), 0, s, map, n_x0, row_mean, row_istd);
+  if (n_tiles > 0)
+    hipLaunchKernelGGL(k_gather, dim3(n_tiles), dim3(256), 0, s, map, n_k, n_x0, row_mean, row_istd,
+                       reinterpret_cast<const int2*>(origins), tiles);
+  return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
+}
+
+extern "C" fh_status fh_propose(fh_cnn_t h, fh_plan_t ph, const int32_t* map, float* scores, int32_t n_top,
+                                int32_t* tile_ids, void* stream) {
+  if (!h || !ph || !map || !scores || n_top < 0 || (n_top > 0 && !tile_ids)) return FH_EINVAL;
+  fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);
+  const fh::Plan& p = reinterpret_cast<const fh::Plan&>(*ph);
+  const int n_k = p.desc.n_k, n_x0 = p.n_x0;
+  const int ta = (n_k + HW - 1) / HW, tb = (n_x0 + HW - 1) / HW;
+  const int n_tiles = ta * tb;
+  if (n_top > n_tiles) return FH_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (c->row_cap < n_k) {
+    if (c->row_mean) (void)hipFree(c->row_mean);
+    if (c->row_istd) (void)hipFree(c->row_istd);
+    c->row_mean = c->row_istd = nullptr;
+    c->row_cap = 0;
+    if (!dalloc(&c->row_mean, n_k) || !dalloc(&c->row_istd, n_k)) return FH_ENOMEM;
+    c->row_cap = n_k;
+  }
+  std::vector<int2> org(n_tiles);
+  for (int a = 0; a < ta; ++a)
+    for (int b = 0; b < tb; ++b) org[(size_t)a * tb + b] = make_int2(a * HW, b * HW);
+  hipLaunchKernelGGL(k_row_stats, dim3(n_k), dim3(256), 0, s, map, n_x0, c->row_mean, c->row_istd);
+  for (int t0 = 0; t0 < n_tiles; t0 += c->max_batch) {
+    const int B = std::min(c->max_batch, n_tiles - t0);
+    if (hipMemcpyAsync(c->origins, org.data() + t0, sizeof(int2) * B, hipMemcpyHostToDevice, s) != hipSuccess)
+      return FH_EDEVICE;
+    hipLaunchKernelGGL(k_gather, dim3(B), dim3(256), 0, s, map, n_k, n_x0, c->row_mean, c->row_istd, c->origins,
+                       c->x);
+    // the network reads its input buffer in place
+    fh_status st = fh_cnn_forward(h, c->x, B, scores + t0, stream);
+    if (st != FH_OK) return st;
+    // the origins buffer is reused by the next batch: finish this one first
+    if (hipStreamSynchronize(s) != hipSuccess) return FH_EDEVICE;
+  }
+  std::vector<float> sc(n_tiles);
+  if (hipMemcpyAsync(sc.data(), scores, sizeof(float) * n_tiles, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FH_EDEVICE;
+  std::vector<int32_t> idx(n_tiles);
+  for (int i = 0; i < n_tiles; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return sc[x] > sc[y]; });
+  for (int i = 0; i < n_top; ++i) tile_ids[i] = idx[i];
+  return FH_OK;
+}

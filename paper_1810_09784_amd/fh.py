@@ -83,6 +83,17 @@ SIGNATURES = {
                                    C.c_void_p]),
     "fh_select": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SelectOpts), C.c_void_p, C.c_int32,
                             C.POINTER(C.c_int32), C.c_void_p]),
+    "fh_cnn_create": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p)]),
+    "fh_cnn_destroy": (None, [C.c_void_p]),
+    "fh_cnn_num_params": (C.c_int64, []),
+    "fh_cnn_set_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "fh_cnn_get_params": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64]),
+    "fh_cnn_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "fh_cnn_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "fh_cnn_step": (C.c_int, [C.c_void_p, C.c_float, C.c_void_p]),
+    "fh_tiles": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                           C.c_void_p, C.c_void_p]),
+    "fh_propose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "fh_status_str": (C.c_char_p, [C.c_int]),
     "fh_version": (C.c_char_p, []),
 }
@@ -280,3 +291,82 @@ def fh_hough_batched(plans: List[Plan], peaks: List[tuple], maps: List, stream=N
     M = (C.c_void_p * m)(*[_ptr(x) for x in maps])
     _check(lib().fh_hough_batched(m, P, K, M, _stream(stream)), "fh_hough_batched")
     return maps
+
+
+class CNN:
+    """fh_cnn_*: the tile network (BF16 matrix-core kernels, FP32 master weights)."""
+
+    def __init__(self, max_batch: int = 256):
+        h = C.c_void_p()
+        _check(lib().fh_cnn_create(int(max_batch), C.byref(h)), "fh_cnn_create")
+        self.handle = h
+        self.max_batch = int(max_batch)
+        self.n_params = int(lib().fh_cnn_num_params())
+
+    def set_params(self, theta):
+        a = np.ascontiguousarray(theta, dtype=np.float32)
+        assert a.size == self.n_params
+        _check(lib().fh_cnn_set_params(self.handle, a.ctypes.data, a.size), "fh_cnn_set_params")
+
+    def get_params(self):
+        p = np.empty(self.n_params, dtype=np.float32)
+        g = np.empty(self.n_params, dtype=np.float32)
+        _check(lib().fh_cnn_get_params(self.handle, p.ctypes.data, g.ctypes.data, p.size), "fh_cnn_get_params")
+        return p, g
+
+    def forward(self, tiles, out=None, stream=None):
+        """tiles: bfloat16 CUDA tensor [B, 64, 64]; returns float32 logits [B]."""
+        import torch
+        assert tiles.dtype == torch.bfloat16 and tiles.is_contiguous() and tuple(tiles.shape[1:]) == (64, 64)
+        B = int(tiles.shape[0])
+        if out is None:
+            out = torch.empty(B, dtype=torch.float32, device=tiles.device)
+        _check(lib().fh_cnn_forward(self.handle, C.c_void_p(_ptr(tiles)), B, C.c_void_p(_ptr(out)),
+                                    _stream(stream)), "fh_cnn_forward")
+        return out
+
+    def backward(self, labels, stream=None):
+        """labels: float32 CUDA tensor [B] of the last forward; returns the loss tensor."""
+        import torch
+        loss = torch.empty(1, dtype=torch.float32, device=labels.device)
+        _check(lib().fh_cnn_backward(self.handle, C.c_void_p(_ptr(labels)), int(labels.numel()),
+                                     C.c_void_p(_ptr(loss)), _stream(stream)), "fh_cnn_backward")
+        return loss
+
+    def step(self, lr: float, stream=None):
+        _check(lib().fh_cnn_step(self.handle, float(lr), _stream(stream)), "fh_cnn_step")
+
+    def destroy(self):
+        if self.handle:
+            lib().fh_cnn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def fh_tiles(hmap, origins, stream=None):
+    """Normalised BF16 tiles [n, 64, 64] of an int32 CUDA map at origins (int32 CUDA [n, 2])."""
+    import torch
+    n_k, n_x0 = hmap.shape
+    n = int(origins.shape[0])
+    tiles = torch.empty((n, 64, 64), dtype=torch.bfloat16, device=hmap.device)
+    mean = torch.empty(n_k, dtype=torch.float32, device=hmap.device)
+    istd = torch.empty(n_k, dtype=torch.float32, device=hmap.device)
+    _check(lib().fh_tiles(C.c_void_p(_ptr(hmap)), n_k, n_x0, C.c_void_p(_ptr(origins)), n, C.c_void_p(_ptr(tiles)),
+                          C.c_void_p(_ptr(mean)), C.c_void_p(_ptr(istd)), _stream(stream)), "fh_tiles")
+    return tiles
+
+
+def fh_propose(net: CNN, plan: Plan, hmap, n_top: int, stream=None):
+    """(scores [n_tiles] CUDA float32, best tile indices as a list)."""
+    import torch
+    ta, tb = (plan.n_k + 63) // 64, (plan.n_x0 + 63) // 64
+    scores = torch.empty(ta * tb, dtype=torch.float32, device=hmap.device)
+    ids = np.zeros(max(1, n_top), dtype=np.int32)
+    _check(lib().fh_propose(net.handle, plan.handle, C.c_void_p(_ptr(hmap)), C.c_void_p(_ptr(scores)), int(n_top),
+                            ids.ctypes.data, _stream(stream)), "fh_propose")
+    return scores, [int(i) for i in ids[:n_top]]
