@@ -1,0 +1,213 @@
+"""The learned tile proposer: data, training and the comparison with the plain
+candidate selection.
+
+Maps.  Many small maps are needed, so their peakmaps are drawn on the GPU
+(torch, seeded) with the model of synth.py: Exp(1) pixel powers, a peak is a
+local maximum >= 2.5 (edge bins excluded), an injected power-law signal puts
+|z + sqrt(a)|^2 (z circular complex Gaussian) into the bin holding f(t) at each
+FFT mid-time.  Geometry of every map: n = 5, 500-600 Hz, T_FFT = 2 s, 7200
+FFTs (4 h), 128 uniform k rows on [0, 2 k_ref) with k_ref the k of
+(f0 = 580 Hz, tau = 1e4 s), 323 x0 columns -> 2 x 6 tiles of 64 x 64.
+Injections: f0 ~ U(505, 595) Hz, k ~ U(0.1, 1.9) k_ref, amplitude a.
+
+Training.  Positive tiles: the tile holding an injection's true (x0, k) cell,
+a log-uniform in [0.25, 6] (weaker signals leave no trace to learn from);
+negative tiles: all tiles of noise-only maps.
+Rows are normalised by their map row's mean and standard deviation.
+
+Evaluation.  A map is detected by a pipeline when one of its candidates has
+CR >= its threshold and lies within 3 bins (Euclidean, in x0 and k bins) of
+the injection's true cell.  Plain: the candidates of fh_select (4 x 6
+squares, second candidate 3 k rows away).  Learned: the same candidates
+restricted to the network's top tile(s).  Each pipeline's CR threshold is set
+on noise-only maps so that the fraction of noise maps with a candidate above
+it (the false-alarm probability per map) is the target FAP."""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+N_BRAKE, F_MIN, F_MAX, TFFT, N_FFT, N_K = 5.0, 500.0, 600.0, 2.0, 7200, 128
+F_REF, TAU_REF = 580.0, 1e4
+THETA = 2.5
+SQ_K, SQ_X0 = 4, 6
+
+
+def k_ref() -> float:
+    return 1.0 / (TAU_REF * (N_BRAKE - 1.0) * F_REF ** (N_BRAKE - 1.0))
+
+
+def k_grid() -> np.ndarray:
+    return np.arange(N_K, dtype=np.float64) * ((2.0 * k_ref()) / N_K)
+
+
+class MapFactory:
+    """Peakmaps of the evaluation geometry, drawn on the GPU in batches."""
+
+    def __init__(self, dev, seed: int):
+        import torch
+        from . import fh
+        self.torch = torch
+        self.dev = dev
+        self.gen = torch.Generator(device=dev)
+        self.gen.manual_seed(int(seed))
+        self.n_f = int(round((F_MAX - F_MIN) * TFFT))
+        self.plan = fh.Plan(N_BRAKE, TFFT, F_MIN, F_MAX, N_FFT, k_grid())
+        self.t = (torch.arange(N_FFT, dtype=torch.float64, device=dev) + 0.5) * TFFT
+        self.x0_min, self.dx0 = self.plan.info.x0_min, self.plan.info.dx0
+
+    def true_cell(self, f0: float, k: float) -> Tuple[int, int]:
+        col = int(math.floor((f0 ** (1.0 - N_BRAKE) - self.x0_min) / self.dx0))
+        row = int(math.floor(k / (2.0 * k_ref() / N_K) + 0.5))
+        return row, col
+
+    def draw(self, inj: List[Tuple[float, float, float]]):
+        """One peakmap per entry (f0, k, a); a <= 0 means noise only.
+        Returns a list of (row_ptr, bin) int32 CUDA tensors."""
+        torch = self.torch
+        B = len(inj)
+        p = -torch.log1p(-torch.rand((B, N_FFT, self.n_f), generator=self.gen, device=self.dev))
+        for b, (f0, k, a) in enumerate(inj):
+            if a <= 0:
+                continue
+            # power law of Sec. II at the FFT mid-times
+            f = f0 / (1.0 + k * (N_BRAKE - 1.0) * f0 ** (N_BRAKE - 1.0) * self.t) ** (1.0 / (N_BRAKE - 1.0))
+            j = torch.floor((f - F_MIN) * TFFT)
+            ok = (j >= 0) & (j < self.n_f)
+            i_idx = torch.nonzero(ok).squeeze(1)
+            j_idx = j[ok].long()
+            g = torch.randn((2, i_idx.numel()), generator=self.gen, device=self.dev)
+            re = g[0] * math.sqrt(0.5) + math.sqrt(a)
+            im = g[1] * math.sqrt(0.5)
+            p[b, i_idx, j_idx] = re * re + im * im
+        c = p[:, :, 1:-1]
+        m = (c >= THETA) & (c > p[:, :, :-2]) & (c > p[:, :, 2:])
+        out = []
+        for b in range(B):
+            nz = torch.nonzero(m[b])
+            counts = torch.bincount(nz[:, 0], minlength=N_FFT)
+            rp = torch.zeros(N_FFT + 1, dtype=torch.int32, device=self.dev)
+            rp[1:] = torch.cumsum(counts, 0).to(torch.int32)
+            out.append((rp.contiguous(), (nz[:, 1] + 1).to(torch.int32).contiguous()))
+        return out
+
+    def hough(self, peaks):
+        from . import fh
+        return [fh.fh_hough(self.plan, rp, bn) for rp, bn in peaks]
+
+
+def random_injection(rng: np.random.Generator, a: float):
+    return float(rng.uniform(505.0, 595.0)), float(rng.uniform(0.1, 1.9) * k_ref()), float(a)
+
+
+def tile_of(row: int, col: int) -> int:
+    n_tb = (323 + 63) // 64
+    return (row // 64) * n_tb + (col // 64)
+
+
+def build_training_set(dev, n_pos: int, n_neg_maps: int, seed: int, batch: int = 32, amp_lo: float = 0.25,
+                       amp_hi: float = 6.0):
+    """(tiles bf16 [N, 64, 64], labels float32 [N]) on the GPU."""
+    import torch
+    from . import fh
+    rng = np.random.default_rng(seed)
+    fac = MapFactory(dev, seed + 1)
+    org = torch.tensor([[64 * (t // 6), 64 * (t % 6)] for t in range(12)], dtype=torch.int32, device=dev)
+    tiles, labels = [], []
+    for b0 in range(0, n_pos, batch):
+        inj = [random_injection(rng, math.exp(rng.uniform(math.log(amp_lo), math.log(amp_hi))))
+               for _ in range(min(batch, n_pos - b0))]
+        maps = fac.hough(fac.draw(inj))
+        for (f0, k, a), H in zip(inj, maps):
+            r, c = fac.true_cell(f0, k)
+            t = tile_of(min(r, N_K - 1), min(max(c, 0), 322))
+            tiles.append(fh.fh_tiles(H, org[t:t + 1].contiguous()))
+            labels.append(1.0)
+    for b0 in range(0, n_neg_maps, batch):
+        maps = fac.hough(fac.draw([(0.0, 0.0, 0.0)] * min(batch, n_neg_maps - b0)))
+        for H in maps:
+            tiles.append(fh.fh_tiles(H, org))
+            labels.extend([0.0] * 12)
+    X = torch.cat(tiles, 0).contiguous()
+    y = torch.tensor(labels, dtype=torch.float32, device=dev)
+    return X, y
+
+
+def train(net, X, y, epochs: int, lr: float, batch: int, seed: int, log=None) -> List[float]:
+    import torch
+    g = torch.Generator(device="cpu")
+    g.manual_seed(seed)
+    n = X.shape[0]
+    hist = []
+    for ep in range(epochs):
+        perm = torch.randperm(n, generator=g).to(X.device)
+        tot, cnt = 0.0, 0
+        for b0 in range(0, n - batch + 1, batch):
+            idx = perm[b0:b0 + batch]
+            net.forward(X[idx].contiguous())
+            loss = net.backward(y[idx].contiguous())
+            net.step(lr)
+            tot += float(loss.item())
+            cnt += 1
+        hist.append(tot / max(cnt, 1))
+        if log:
+            log(f"epoch {ep}: loss {hist[-1]:.4f}")
+    return hist
+
+
+def map_statistics(fac: MapFactory, net, inj: List[Tuple[float, float, float]], n_top: int = 1):
+    """Per map: (best CR of any plain candidate near the true cell or anywhere for
+    noise, same restricted to proposed tiles, proposed tiles, injection tile)."""
+    from . import fh
+    out = []
+    maps = fac.hough(fac.draw(inj))
+    for (f0, k, a), H in zip(inj, maps):
+        cands, _ = fh.fh_select(fac.plan, H, SQ_K, SQ_X0, 3)
+        _, top = fh.fh_propose(net, fac.plan, H, n_top)
+        tops = set(top)
+        if a > 0:
+            r, c = fac.true_cell(f0, k)
+            near = [x for x in cands if math.hypot(x["row"] - r, x["col"] - c) <= 3.0]
+        else:
+            near = cands
+        plain = max([x["cr"] for x in near], default=-math.inf)
+        learned = max([x["cr"] for x in near if tile_of(x["row"], x["col"]) in tops], default=-math.inf)
+        out.append((plain, learned))
+    return out
+
+
+def threshold_for_fap(noise_scores: np.ndarray, fap: float) -> float:
+    """Smallest threshold whose exceedance fraction on noise maps is <= fap."""
+    s = np.sort(np.asarray(noise_scores))[::-1]
+    k = int(math.floor(fap * len(s)))
+    if k >= len(s):
+        return -math.inf
+    return float(np.nextafter(s[k], np.inf)) if np.isfinite(s[k]) else -math.inf
+
+
+def evaluate(dev, net, amps, n_noise: int, n_per_amp: int, seed: int, fap: float, batch: int = 32, log=None):
+    rng = np.random.default_rng(seed)
+    fac = MapFactory(dev, seed + 7)
+    noise = []
+    for b0 in range(0, n_noise, batch):
+        noise += map_statistics(fac, net, [(0.0, 0.0, 0.0)] * min(batch, n_noise - b0))
+    noise = np.array(noise)
+    thr_plain = threshold_for_fap(noise[:, 0], fap)
+    thr_learn = threshold_for_fap(noise[:, 1], fap)
+    res: Dict[str, object] = {"fap": fap, "n_noise_maps": n_noise, "thr_plain": thr_plain, "thr_learned": thr_learn,
+                              "fap_plain": float(np.mean(noise[:, 0] >= thr_plain)),
+                              "fap_learned": float(np.mean(noise[:, 1] >= thr_learn)),
+                              "tiles_touched_frac": 1.0 / 12.0, "curve": []}
+    for a in amps:
+        st = []
+        for b0 in range(0, n_per_amp, batch):
+            st += map_statistics(fac, net, [random_injection(rng, a) for _ in range(min(batch, n_per_amp - b0))])
+        st = np.array(st)
+        e_p = float(np.mean(st[:, 0] >= thr_plain))
+        e_l = float(np.mean(st[:, 1] >= thr_learn))
+        res["curve"].append({"amp": a, "n": n_per_amp, "eff_plain": e_p, "eff_learned": e_l})
+        if log:
+            log(f"a = {a}: plain {e_p:.3f}, learned {e_l:.3f}")
+    return res

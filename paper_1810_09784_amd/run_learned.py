@@ -1,0 +1,79 @@
+"""Train the tile CNN on the GPU and compare it with the plain selection.
+
+python -m paper_1810_09784_amd.run_learned --out DIR [--pos 10000 --neg-maps 850 --epochs 12]
+
+Writes DIR/tile_cnn.npy (float32 parameters) and DIR/learned.json (training
+loss per epoch, thresholds at the target false-alarm probability and the
+detection-efficiency curves of both pipelines).  Progress on stderr."""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--pos", type=int, default=10000)
+    ap.add_argument("--neg-maps", type=int, default=850)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--lr", type=float, default=3e-4)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--noise-maps", type=int, default=5000)
+    ap.add_argument("--per-amp", type=int, default=400)
+    ap.add_argument("--amps", default="0.3,0.4,0.5,0.7,1.0,1.5,2.0")
+    ap.add_argument("--amp-lo", type=float, default=0.25)
+    ap.add_argument("--amp-hi", type=float, default=6.0)
+    ap.add_argument("--fap", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--weights", default=None, help="skip training, evaluate these parameters")
+    a = ap.parse_args()
+    import torch
+    from . import fh, learn
+
+    def log(*x):
+        print(*x, file=sys.stderr, flush=True)
+
+    os.makedirs(a.out, exist_ok=True)
+    dev = torch.device("cuda:0")
+    net = fh.CNN(max_batch=max(a.batch, 64))
+    res = {"config": vars(a)}
+    if a.weights:
+        net.set_params(np.load(a.weights))
+    else:
+        rng = np.random.default_rng(a.seed)
+        # He-normal conv weights, zero biases, small head
+        th = []
+        for ci, co in ((1, 16), (16, 32), (32, 64), (64, 64)):
+            th += [rng.normal(0, np.sqrt(2.0 / (9 * ci)), co * 9 * ci), np.zeros(co)]
+        th += [rng.normal(0, 0.1, 64), np.zeros(1)]
+        net.set_params(np.concatenate(th))
+        t = time.time()
+        X, y = learn.build_training_set(dev, a.pos, a.neg_maps, a.seed, amp_lo=a.amp_lo, amp_hi=a.amp_hi)
+        torch.cuda.synchronize()
+        log(f"training set: {X.shape[0]} tiles ({int(y.sum().item())} positive) in {time.time() - t:.1f} s")
+        t = time.time()
+        hist = learn.train(net, X, y, a.epochs, a.lr, a.batch, a.seed, log=log)
+        torch.cuda.synchronize()
+        dt = time.time() - t
+        steps = a.epochs * (X.shape[0] // a.batch)
+        flop = steps * a.batch * 3 * 492.4e6
+        res["training"] = {"loss": hist, "seconds": dt, "steps": steps, "tiles_per_s": steps * a.batch / dt,
+                           "approx_tflops": flop / dt / 1e12}
+        p, _ = net.get_params()
+        np.save(os.path.join(a.out, "tile_cnn.npy"), p)
+        del X, y
+    t = time.time()
+    amps = [float(x) for x in a.amps.split(",")]
+    res["evaluation"] = learn.evaluate(dev, net, amps, a.noise_maps, a.per_amp, a.seed + 100, a.fap, log=log)
+    res["evaluation"]["seconds"] = time.time() - t
+    with open(os.path.join(a.out, "learned.json"), "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res["evaluation"]))
+
+
+if __name__ == "__main__":
+    main()
