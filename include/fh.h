@@ -160,9 +160,12 @@ typedef struct {
   double x0, k, f0, fdot0;
 } fh_candidate;
 
-/* Select candidates of a Hough map (DEVICE int32 [n_k][n_x0], as written by
- * fh_hough with this plan).  Reads the map once on `stream`, copies the
- * per-row partial sums to the host and finishes there; synchronises `stream`.
+/* Select candidates of a Hough map (DEVICE int32 [n_k][n_x0], counts >= 0, as
+ * written by fh_hough with this plan).  Reads the map once on `stream` (per
+ * row and column segment: exact sums and best cell), reduces the rows of each
+ * square on the device, copies 48 bytes per square to the host and evaluates
+ * mu, sigma and CR there; synchronises `stream`.  The plan's selection scratch
+ * (8 (3 n_k sq_x0 + 6 sq_k sq_x0) bytes) is allocated on first use or growth.
  * Writes min(total, cap) candidates to `out` (HOST) and the total number with
  * CR >= cr_thr to *n_out.  Errors: FH_EINVAL (NULL pointers, sq_k outside
  * [1, n_k], sq_x0 outside [1, min(W, 256)], bad column range), FH_EDEVICE. */

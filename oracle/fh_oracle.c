@@ -58,6 +58,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_EINVAL -1
@@ -206,4 +209,13 @@ int orc_pair_interval(const orc_desc* d, int32_t r, int32_t i, int32_t j, int32_
   *b_lo_out = (int32_t)(b_lo > 2e9 ? 2e9 : b_lo);
   *b_hi_out = (int32_t)(b_hi < -2e9 ? -2e9 : b_hi);
   return b_hi >= b_lo ? (int)(b_hi - b_lo + 1.0) : 0;
+}
+
+/* Threads the row loop of orc_hough_rows runs on (1 without OpenMP). */
+int orc_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -49,8 +49,15 @@ def lib():
         L.orc_hough_rows.argtypes = [C.POINTER(OrcDesc), ip, ip, ip, C.c_int32, ip, C.POINTER(C.c_int64)]
         L.orc_pair_interval.restype = C.c_int
         L.orc_pair_interval.argtypes = [C.POINTER(OrcDesc), C.c_int32, C.c_int32, C.c_int32, ip, ip]
+        L.orc_threads.restype = C.c_int
+        L.orc_threads.argtypes = []
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """Threads the oracle's row loop uses."""
+    return int(lib().orc_threads())
 
 
 def _dptr(a: Optional[np.ndarray]):

@@ -455,19 +455,30 @@ __global__ void k_prologue(MapArgs M0, const MapArgs* __restrict__ maps, int n_m
   }
 }
 
-// Rank structure of the windowed mode and bad-peak counting, one wavefront
-// per FFT: the FFT's peaks (lanes, coalesced) add into per-word counts and OR
-// their bits into per-word masks in LDS; an exclusive scan of the counts
-// gives the peaks below each word.  Entry w of FFT i is stored at
-// rank[w * n_fft + i] as (mask << 32 | peaks below), so that the kernel's
-// lanes (consecutive FFTs) read it coalesced.  Maps with more words than the
-// LDS holds take the per-(FFT, word) binary search instead.
+// Rank structure of the windowed mode and bad-peak counting.  A work-group
+// takes a group of F consecutive FFTs, one wavefront per FFT: the FFT's peaks
+// (lanes, coalesced) add into per-word counts and OR their bits into per-word
+// masks in the wave's LDS scratch; an exclusive scan of the counts gives the
+// peaks below each word.  The group's entries collect in LDS and leave as
+// runs of F consecutive FFTs: entry w of FFT i is stored at
+// rank[w * n_fft + i] as (mask << 32 | peaks below), so that the tile
+// kernel's lanes (consecutive FFTs) read it coalesced.  Maps with more words
+// than the LDS holds take the per-(FFT, word) binary search instead.
 constexpr int kPrepWaves = 8;
 constexpr int kPrepMaxWords = 512;
+constexpr int kPrepLdsWords = 16384;  // 64 KB of dynamic LDS per work-group
 
-__device__ void prepare_fft_lds(const MapArgs& M, int i, int lane, unsigned* cnt, unsigned* msk) {
+// FFTs per group: the largest power of two <= 64 whose entries (row pitch
+// F + 1 u64) fit beside the waves' scratch.
+__device__ __forceinline__ int prep_group(int n_words) {
+  int F = 64;
+  while (F > 1 && (F + 1) * n_words * 2 + kPrepWaves * 2 * n_words > kPrepLdsWords) F >>= 1;
+  return F;
+}
+
+__device__ void prepare_fft_lds(const MapArgs& M, int i, int lane, unsigned* cnt, unsigned* msk,
+                                unsigned long long* rbuf, int pitch) {
   const GMap G(M);
-  gptr<unsigned long long> rank = (gptr<unsigned long long>)M.rank;
   const int lo = min(max(G.row_ptr[i], 0), M.n_peaks);
   const int hi = min(max(G.row_ptr[i + 1], lo), M.n_peaks);
   for (int w = lane; w < M.n_words; w += kWave) {
@@ -475,33 +486,39 @@ __device__ void prepare_fft_lds(const MapArgs& M, int i, int lane, unsigned* cnt
     msk[w] = 0;
   }
   wave_sync_lds();
-  unsigned long long bad = 0;
-  for (int p = lo + lane; p < hi; p += kWave) {
-    const int j = G.bin[p];
-    const int jm = p > lo ? G.bin[p - 1] : INT_MIN;
-    if (j <= jm) ++bad;  // not ascending
-    if (j < 0 || j >= M.n_f) {
-      ++bad;
-    } else {
-      atomicAdd(&cnt[j >> 5], 1u);
-      atomicOr(&msk[j >> 5], 1u << (j & 31));
+  int bad = 0, neg = 0;
+  int last = INT_MIN;  // bin of the previous peak of this FFT
+  for (int p0 = lo; p0 < hi; p0 += kWave) {
+    const int p = p0 + lane;
+    const bool v = p < hi;
+    const int j = v ? G.bin[p] : 0;
+    int jm = __shfl_up(j, 1);
+    if (lane == 0) jm = last;
+    last = __shfl(j, kWave - 1);
+    if (v) {
+      bad += j <= jm;  // not ascending
+      if (j < 0 || j >= M.n_f) {
+        ++bad;
+        neg += j < 0;
+      } else {
+        atomicAdd(&cnt[j >> 5], 1u);
+        atomicOr(&msk[j >> 5], 1u << (j & 31));
+      }
     }
   }
   wave_sync_lds();
   // negative bins sit before word 0: they shift every word's position
-  int neg = 0;
-  for (int p = lo + lane; p < hi; p += kWave) neg += G.bin[p] < 0;
   neg = wave_incl_scan(neg);
   unsigned carry = (unsigned)__builtin_amdgcn_readlane(neg, 63);
   for (int w0 = 0; w0 < M.n_words; w0 += kWave) {
     const int w = w0 + lane;
     const unsigned c = w < M.n_words ? cnt[w] : 0u;
     const unsigned incl = (unsigned)wave_incl_scan((int)c) + carry;
-    if (w < M.n_words) rank[(size_t)w * M.n_fft + i] = ((unsigned long long)msk[w] << 32) | (incl - c);
+    if (w < M.n_words) rbuf[(size_t)w * pitch] = ((unsigned long long)msk[w] << 32) | (incl - c);
     carry = (unsigned)__builtin_amdgcn_readlane((int)incl, 63);
   }
-  bad = (unsigned long long)wave_incl_scan((int)bad);
-  if (lane == 63 && bad) atomicAdd(M.err, bad);
+  bad = wave_incl_scan(bad);
+  if (lane == 63 && bad) atomicAdd(M.err, (unsigned long long)bad);
   wave_sync_lds();
 }
 
@@ -534,12 +551,29 @@ __device__ void prepare_word(const MapArgs& M, long long t) {
   if (bad) atomicAdd(M.err, bad);
 }
 
+// Whole grid over one map.  Every branch and trip count around the barriers
+// is uniform over the work-group.
 __device__ void prepare_map(const MapArgs& M, unsigned* lds) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (M.n_words <= kPrepMaxWords) {
-    unsigned* cnt = lds + wave * 2 * kPrepMaxWords;
-    for (int i = blockIdx.x * kPrepWaves + wave; i < M.n_fft; i += gridDim.x * kPrepWaves)
-      prepare_fft_lds(M, i, lane, cnt, cnt + kPrepMaxWords);
+    const int F = prep_group(M.n_words);
+    const int pitch = F + 1;
+    unsigned* cnt = lds + wave * 2 * M.n_words;
+    unsigned long long* rbuf = (unsigned long long*)(lds + kPrepWaves * 2 * M.n_words);
+    gptr<unsigned long long> rank = (gptr<unsigned long long>)M.rank;
+    const int n_groups = (M.n_fft + F - 1) / F;
+    for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
+      const int i0 = g * F;
+      const int nf = min(F, M.n_fft - i0);
+      for (int f = wave; f < nf; f += kPrepWaves) prepare_fft_lds(M, i0 + f, lane, cnt, cnt + M.n_words, rbuf + f, pitch);
+      __syncthreads();
+      const int n = M.n_words * F;
+      for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int w = e / F, f = e - w * F;
+        if (f < nf) rank[(size_t)w * M.n_fft + i0 + f] = rbuf[w * pitch + f];
+      }
+      __syncthreads();
+    }
   } else {
     const long long n = (long long)M.n_fft * M.n_words;
     for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
@@ -548,16 +582,16 @@ __device__ void prepare_map(const MapArgs& M, unsigned* lds) {
 }
 
 __global__ void __launch_bounds__(kPrepWaves * 64) k_prepare(MapArgs M) {
-  __shared__ unsigned lds[kPrepWaves * 2 * kPrepMaxWords];
-  prepare_map(M, lds);
+  extern __shared__ unsigned prep_lds[];
+  prepare_map(M, prep_lds);
 }
 
 // All windowed maps of a batch, one after the other over the whole grid.
 __global__ void __launch_bounds__(kPrepWaves * 64) k_prepare_batch(const MapArgs* __restrict__ maps, int m) {
-  __shared__ unsigned lds[kPrepWaves * 2 * kPrepMaxWords];
+  extern __shared__ unsigned prep_lds[];
   for (int q = 0; q < m; ++q) {
     const MapArgs M = maps[q];
-    if (M.mode == kModeWindowed) prepare_map(M, lds);
+    if (M.mode == kModeWindowed) prepare_map(M, prep_lds);
   }
 }
 
@@ -598,7 +632,7 @@ fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStrea
                      (const MapArgs*)nullptr, 1, (const int4*)p.dClears, n_clears, p.dHead);
   if (check_launch() != FH_OK) return FH_EDEVICE;
   if (a.mode == kModeWindowed) {
-    hipLaunchKernelGGL(k_prepare, dim3(2048), dim3(kPrepWaves * 64), 0, s, a);
+    hipLaunchKernelGGL(k_prepare, dim3(2048), dim3(kPrepWaves * 64), kPrepLdsWords * 4, s, a);
     if (check_launch() != FH_OK) return FH_EDEVICE;
   }
   const int th = p.tile.threads;
@@ -726,7 +760,8 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
     hipLaunchKernelGGL(k_prologue, dim3((unsigned)std::max(1, std::min(b->n_clears, 1024))), dim3(256), 0, b->cap,
                        none, (const MapArgs*)b->d_maps, m, (const int4*)b->d_clears, b->n_clears, b->d_head);
     if (any_windowed)
-      hipLaunchKernelGGL(k_prepare_batch, dim3(2048), dim3(kPrepWaves * 64), 0, b->cap, b->d_maps, m);
+      hipLaunchKernelGGL(k_prepare_batch, dim3(2048), dim3(kPrepWaves * 64), kPrepLdsWords * 4, b->cap, b->d_maps,
+                         m);
     hipLaunchKernelGGL((k_queue<256, true>), dim3(b->grid), dim3(256), lds, b->cap, none, (const MapArgs*)b->d_maps,
                        (const Unit*)b->d_queue, b->n_queue, b->d_head);
     ok = hipStreamEndCapture(b->cap, &b->graph) == hipSuccess;

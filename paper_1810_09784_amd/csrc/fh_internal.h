@@ -77,7 +77,8 @@ struct Plan {
   Unit* dUnits = nullptr;
   int4* dClears = nullptr;
   int32_t* dHead = nullptr;
-  unsigned long long* dSel = nullptr;  // [n_k][kMaxSelectSegments][3] partial sums of fh_select
+  unsigned long long* dSel = nullptr;  // fh_select scratch: row segment partials, then square results
+  size_t sel_words = 0;               // its capacity in 64-bit words (grows on demand)
   int32_t grid = 0;  // persistent work-groups of a single-map launch
   int device = 0;
   int n_cu = 256;

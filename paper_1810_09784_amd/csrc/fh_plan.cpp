@@ -244,6 +244,7 @@ static void free_dev(Plan& p) {
   if (p.dHead) (void)hipFree(p.dHead);
   if (p.dSel) (void)hipFree(p.dSel);
   p.dSel = nullptr;
+  p.sel_words = 0;
   p.dUnits = nullptr;
   p.dClears = nullptr;
   p.dHead = nullptr;
@@ -418,7 +419,6 @@ extern "C" fh_status fh_plan(const fh_map_desc* d, const fh_tile_cfg* cfg, fh_pl
   if (st == FH_OK) st = upload<Unit>(&p.dUnits, p.units.data(), p.units.size());
   if (st == FH_OK) st = upload<int4>(&p.dClears, p.clears.data(), p.clears.size());
   if (st == FH_OK) st = upload<int32_t>(&p.dHead, nullptr, 1);
-  if (st == FH_OK) st = upload<unsigned long long>(&p.dSel, nullptr, (size_t)d->n_k * kMaxSelectSegments * 3);
   if (st == FH_OK && hipMemset(p.dErr, 0, sizeof(unsigned long long)) != hipSuccess) st = FH_EDEVICE;
   if (st != FH_OK) {
     free_dev(p);

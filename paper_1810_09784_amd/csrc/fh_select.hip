@@ -2,14 +2,20 @@
 // (x0, k) plane, the best cell of each square and a second one a few k rows
 // away, scored by the critical ratio CR = (y - mu) / sigma).
 //
-// The device reads the map once: one work-group per map row produces, for
-// every column segment of the square grid, the exact int64 sum and sum of
-// squares of the counts and the row's best cell (largest count, then
-// smallest column).  The host adds the rows of each square, applies the
-// row-major tie rule across rows and evaluates mu, sigma and CR in binary64.
+// Two passes on the device and a small finish on the host:
+//  1. k_select_rows: one work-group per (map row, column segment of the square
+//     grid) reads its part of the row once with 16-byte loads and writes the
+//     exact int64 sum and sum of squares of the counts and the segment's best
+//     cell (largest count, then smallest column);
+//  2. k_select_squares: one work-group per square adds its rows' partials and
+//     picks the best row (largest count, then smallest row) and the best row
+//     at least min_dk rows away from it;
+//  3. the host copies the per-square results (64 bytes each) and evaluates
+//     mu, sigma and CR in binary64.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -19,9 +25,15 @@
 namespace fh {
 
 constexpr int kSelThreads = 256;
+constexpr int kSelWaves = kSelThreads / 64;
+constexpr int kSqWords = 6;  // per square: Sy, Sy2, key1, col1, key2, col2
 
 template <typename T>
 using gsel = __attribute__((address_space(1))) T*;
+typedef int v4s __attribute__((ext_vector_type(4)));
+
+// Order-preserving 32-bit image of a signed count, for packed (count, index) keys.
+__device__ __forceinline__ unsigned long long biased(int y) { return (unsigned long long)((unsigned)y ^ 0x80000000u); }
 
 __device__ __forceinline__ long long wave_sum_i64(long long x) {
   for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o);
@@ -36,52 +48,142 @@ __device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x)
   return x;
 }
 
-// out[(r * sq_x0 + b) * 3 + {0, 1, 2}] = Sy, Sy2, (count << 32 | ~column)
+// Sums and maximum over the work-group; the result is valid in thread 0.
+__device__ __forceinline__ void block_reduce(long long& sy, long long& sy2, unsigned long long& key) {
+  __shared__ long long s_sy[kSelWaves], s_sy2[kSelWaves];
+  __shared__ unsigned long long s_key[kSelWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  sy = wave_sum_i64(sy);
+  sy2 = wave_sum_i64(sy2);
+  key = wave_max_u64(key);
+  if (lane == 0) {
+    s_sy[wave] = sy;
+    s_sy2[wave] = sy2;
+    s_key[wave] = key;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kSelWaves; ++w) {
+      sy += s_sy[w];
+      sy2 += s_sy2[w];
+      key = s_key[w] > key ? s_key[w] : key;
+    }
+  }
+}
+
+struct SegAcc {
+  long long sy = 0, sy2 = 0;
+  int best = INT_MIN, col = -1;
+  __device__ __forceinline__ void add(int y, int c) {  // columns arrive in ascending order per thread
+    sy += y;
+    sy2 += (long long)y * y;
+    if (y > best || col < 0) {
+      best = y;
+      col = c;
+    }
+  }
+};
+
+// out[(r * sq_x0 + b) * 3 + {0, 1, 2}] = Sy, Sy2, (biased count << 32 | ~column)
+// Grid: (n_k, sq_x0).  Segment b covers columns col_lo + floor(b W / sq_x0) ..
+// col_lo + floor((b+1) W / sq_x0) - 1.
 __global__ void __launch_bounds__(kSelThreads) k_select_rows(const int32_t* map_, int n_x0, int col_lo, int col_hi,
                                                               int sq_x0, unsigned long long* out_) {
   const gsel<const int32_t> map = (gsel<const int32_t>)map_;
-  const gsel<unsigned long long> out = (gsel<unsigned long long>)out_;
-  __shared__ long long s_sy[kSelThreads / 64], s_sy2[kSelThreads / 64];
-  __shared__ unsigned long long s_mx[kSelThreads / 64];
-  const int r = blockIdx.x;
+  const int r = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
   const int W = col_hi - col_lo;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int s0 = col_lo + (int)((long long)b * W / sq_x0);
+  const int s1 = col_lo + (int)((long long)(b + 1) * W / sq_x0);
   const gsel<const int32_t> row = map + (size_t)r * n_x0;
-  for (int b = 0; b < sq_x0; ++b) {
-    const int s0 = col_lo + (int)((long long)b * W / sq_x0);
-    const int s1 = col_lo + (int)((long long)(b + 1) * W / sq_x0);
-    long long sy = 0, sy2 = 0;
-    unsigned long long mx = 0;
-    for (int c = s0 + threadIdx.x; c < s1; c += kSelThreads) {
-      const int y = row[c];
-      sy += y;
-      sy2 += (long long)y * y;
-      const unsigned long long key = ((unsigned long long)(unsigned)y << 32) | (unsigned)(~(unsigned)c);
-      mx = key > mx ? key : mx;
+  // columns [a0, a1) start on 16-byte boundaries
+  const int head = (int)((4 - (((uintptr_t)(row + s0) >> 2) & 3)) & 3);
+  const int a0 = min(s0 + head, s1);
+  const int a1 = a0 + ((s1 - a0) & ~3);
+  SegAcc acc;
+  if (s0 + t < a0) acc.add(row[s0 + t], s0 + t);
+  const gsel<const v4s> v = (gsel<const v4s>)(row + a0);
+  const int nv = (a1 - a0) >> 2;
+  int q = t;
+  for (; q + 3 * kSelThreads < nv; q += 4 * kSelThreads) {
+    v4s x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = v[q + u * kSelThreads];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = a0 + 4 * (q + u * kSelThreads);
+      acc.add(x[u].x, c);
+      acc.add(x[u].y, c + 1);
+      acc.add(x[u].z, c + 2);
+      acc.add(x[u].w, c + 3);
     }
-    sy = wave_sum_i64(sy);
-    sy2 = wave_sum_i64(sy2);
-    mx = wave_max_u64(mx);
-    if (lane == 0) {
-      s_sy[wave] = sy;
-      s_sy2[wave] = sy2;
-      s_mx[wave] = mx;
+  }
+  for (; q < nv; q += kSelThreads) {
+    const v4s x = v[q];
+    const int c = a0 + 4 * q;
+    acc.add(x.x, c);
+    acc.add(x.y, c + 1);
+    acc.add(x.z, c + 2);
+    acc.add(x.w, c + 3);
+  }
+  if (a1 + t < s1) acc.add(row[a1 + t], a1 + t);
+  unsigned long long key = acc.col >= 0 ? (biased(acc.best) << 32) | (unsigned)(~(unsigned)acc.col) : 0ull;
+  long long sy = acc.sy, sy2 = acc.sy2;
+  block_reduce(sy, sy2, key);
+  if (t == 0) {
+    gsel<unsigned long long> out = (gsel<unsigned long long>)out_ + ((size_t)r * sq_x0 + b) * 3;
+    out[0] = (unsigned long long)sy;
+    out[1] = (unsigned long long)sy2;
+    out[2] = key;
+  }
+}
+
+// Per square (a, b): rows floor(a n_k / sq_k) .. floor((a+1) n_k / sq_k) - 1.
+// sq_out[(a * sq_x0 + b) * 6 + {0..5}] = Sy, Sy2, key1, col1, key2, col2 with
+// key = biased count << 32 | ~row (0 = no such row).  Grid: (sq_k, sq_x0).
+__global__ void __launch_bounds__(kSelThreads) k_select_squares(const unsigned long long* rows_, int n_k, int sq_k,
+                                                                 int sq_x0, int min_dk, unsigned long long* sq_out_) {
+  const gsel<const unsigned long long> rows = (gsel<const unsigned long long>)rows_;
+  __shared__ int s_r1;
+  const int a = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+  const int r0 = (int)((long long)a * n_k / sq_k), r1 = (int)((long long)(a + 1) * n_k / sq_k);
+  long long sy = 0, sy2 = 0;
+  unsigned long long key = 0;
+  for (int r = r0 + t; r < r1; r += kSelThreads) {
+    const gsel<const unsigned long long> e = rows + ((size_t)r * sq_x0 + b) * 3;
+    sy += (long long)e[0];
+    sy2 += (long long)e[1];
+    const unsigned long long k = (e[2] & 0xffffffff00000000ull) | (unsigned)(~(unsigned)r);
+    key = k > key ? k : key;
+  }
+  block_reduce(sy, sy2, key);
+  if (t == 0) s_r1 = key ? (int)~(unsigned)(key & 0xffffffffu) : -1;
+  __syncthreads();
+  const int best_r = s_r1;
+  unsigned long long key2 = 0;
+  if (min_dk >= 1 && best_r >= 0) {
+    for (int r = r0 + t; r < r1; r += kSelThreads) {
+      if (abs(r - best_r) < min_dk) continue;
+      const unsigned long long k = (rows[((size_t)r * sq_x0 + b) * 3 + 2] & 0xffffffff00000000ull) |
+                                   (unsigned)(~(unsigned)r);
+      key2 = k > key2 ? k : key2;
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      long long a = 0, q = 0;
-      unsigned long long m = 0;
-      for (int w = 0; w < kSelThreads / 64; ++w) {
-        a += s_sy[w];
-        q += s_sy2[w];
-        m = s_mx[w] > m ? s_mx[w] : m;
-      }
-      const size_t o = ((size_t)r * sq_x0 + b) * 3;
-      out[o] = (unsigned long long)a;
-      out[o + 1] = (unsigned long long)q;
-      out[o + 2] = m;
-    }
-    __syncthreads();
+  }
+  long long z0 = 0, z1 = 0;
+  __syncthreads();  // block_reduce's LDS is reused
+  block_reduce(z0, z1, key2);
+  if (t == 0) {
+    gsel<unsigned long long> o = (gsel<unsigned long long>)sq_out_ + ((size_t)a * sq_x0 + b) * kSqWords;
+    auto col_of = [&](unsigned long long k) -> unsigned long long {
+      if (!k) return ~0ull;
+      const int r = (int)~(unsigned)(k & 0xffffffffu);
+      return (unsigned long long)(~(unsigned)(rows[((size_t)r * sq_x0 + b) * 3 + 2] & 0xffffffffu));
+    };
+    o[0] = (unsigned long long)sy;
+    o[1] = (unsigned long long)sy2;
+    o[2] = key;
+    o[3] = col_of(key);
+    o[4] = key2;
+    o[5] = col_of(key2);
   }
 }
 
@@ -100,17 +202,38 @@ extern "C" fh_status fh_select(fh_plan_t h, const int32_t* map, const fh_select_
   const int W = col_hi - col_lo;
   if (o->sq_k < 1 || o->sq_k > n_k || o->sq_x0 < 1 || o->sq_x0 > std::min(W, kMaxSelectSegments)) return FH_EINVAL;
   hipStream_t s = (hipStream_t)stream;
-  const int sq_x0 = o->sq_x0;
-  hipLaunchKernelGGL(k_select_rows, dim3(n_k), dim3(kSelThreads), 0, s, map, p.n_x0, col_lo, col_hi, sq_x0,
-                     (unsigned long long*)p.dSel);
+  const int sq_k = o->sq_k, sq_x0 = o->sq_x0;
+  const size_t row_words = (size_t)n_k * sq_x0 * 3;
+  const size_t n_sq = (size_t)sq_k * sq_x0;
+  const size_t need = row_words + n_sq * kSqWords;
+  if (need > p.sel_words) {  // grow the scratch (the previous select on this stream is complete)
+    if (p.dSel) (void)hipFree(p.dSel);
+    p.dSel = nullptr;
+    p.sel_words = 0;
+    const hipError_t e = hipMalloc((void**)&p.dSel, need * sizeof(unsigned long long));
+    if (e != hipSuccess) {
+      p.dSel = nullptr;
+      return e == hipErrorOutOfMemory ? FH_ENOMEM : FH_EDEVICE;
+    }
+    p.sel_words = need;
+  }
+  unsigned long long* d_rows = p.dSel;
+  unsigned long long* d_sq = p.dSel + row_words;
+  hipLaunchKernelGGL(k_select_rows, dim3(n_k, sq_x0), dim3(kSelThreads), 0, s, map, p.n_x0, col_lo, col_hi, sq_x0,
+                     d_rows);
+  hipLaunchKernelGGL(k_select_squares, dim3(sq_k, sq_x0), dim3(kSelThreads), 0, s, d_rows, n_k, sq_k, sq_x0,
+                     o->min_dk, d_sq);
   if (hipGetLastError() != hipSuccess) return FH_EDEVICE;
-  std::vector<unsigned long long> rows((size_t)n_k * sq_x0 * 3);
-  if (hipMemcpyAsync(rows.data(), p.dSel, rows.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+  std::vector<unsigned long long> sq(n_sq * kSqWords);
+  if (hipMemcpyAsync(sq.data(), d_sq, sq.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return FH_EDEVICE;
   int32_t total = 0;
   const double inv1n = 1.0 / (1.0 - p.desc.n);
-  auto emit = [&](int r, int c, int y, int sq, int second, double mu, double sigma) {
+  auto emit = [&](unsigned long long key, unsigned long long col, int sqi, int second, double mu, double sigma) {
+    const int y = (int)((unsigned)(key >> 32) ^ 0x80000000u);
+    const int r = (int)~(unsigned)(key & 0xffffffffu);
+    const int c = (int)col;
     const double cr = ((double)y - mu) / sigma;
     if (!(cr >= o->cr_thr)) return;
     if (total < cap) {
@@ -119,7 +242,7 @@ extern "C" fh_status fh_select(fh_plan_t h, const int32_t* map, const fh_select_
       e.row = r;
       e.col = c;
       e.count = y;
-      e.square = sq;
+      e.square = sqi;
       e.second = second;
       e.cr = cr;
       e.mu = mu;
@@ -131,46 +254,21 @@ extern "C" fh_status fh_select(fh_plan_t h, const int32_t* map, const fh_select_
     }
     ++total;
   };
-  for (int a = 0; a < o->sq_k; ++a) {
-    const int r0 = (int)((long long)a * n_k / o->sq_k), r1 = (int)((long long)(a + 1) * n_k / o->sq_k);
+  for (int a = 0; a < sq_k; ++a) {
+    const long long nr = (long long)(a + 1) * n_k / sq_k - (long long)a * n_k / sq_k;
     for (int b = 0; b < sq_x0; ++b) {
-      const int s0 = col_lo + (int)((long long)b * W / sq_x0), s1 = col_lo + (int)((long long)(b + 1) * W / sq_x0);
-      const long long N = (long long)(r1 - r0) * (s1 - s0);
-      if (N <= 0) continue;
-      long long Sy = 0, Sy2 = 0;
-      int best_r = -1, best_y = -1, best_c = -1;
-      for (int r = r0; r < r1; ++r) {
-        const unsigned long long* e = &rows[((size_t)r * sq_x0 + b) * 3];
-        Sy += (long long)e[0];
-        Sy2 += (long long)e[1];
-        const int y = (int)(e[2] >> 32);
-        if (y > best_y) {  // strictly greater: the smallest row wins ties
-          best_y = y;
-          best_r = r;
-          best_c = (int)(~(unsigned)(e[2] & 0xffffffffu));
-        }
-      }
-      const double mu = (double)Sy / (double)N;
-      const double ex2 = (double)Sy2 / (double)N;
+      const long long nc = (long long)(b + 1) * W / sq_x0 - (long long)b * W / sq_x0;
+      const long long N = nr * nc;
+      const unsigned long long* e = &sq[((size_t)a * sq_x0 + b) * kSqWords];
+      if (N <= 0 || !e[2]) continue;
+      const double mu = (double)(long long)e[0] / (double)N;
+      const double ex2 = (double)(long long)e[1] / (double)N;
       const double var = ex2 - mu * mu;
       const double sigma = std::sqrt(var);
       if (!(sigma > 0.0)) continue;
-      const int sq = a * sq_x0 + b;
-      emit(best_r, best_c, best_y, sq, 0, mu, sigma);
-      if (o->min_dk >= 1) {
-        int r2 = -1, y2 = -1, c2 = -1;
-        for (int r = r0; r < r1; ++r) {
-          if (std::abs(r - best_r) < o->min_dk) continue;
-          const unsigned long long* e = &rows[((size_t)r * sq_x0 + b) * 3];
-          const int y = (int)(e[2] >> 32);
-          if (y > y2) {
-            y2 = y;
-            r2 = r;
-            c2 = (int)(~(unsigned)(e[2] & 0xffffffffu));
-          }
-        }
-        if (r2 >= 0) emit(r2, c2, y2, sq, 1, mu, sigma);
-      }
+      const int sqi = a * sq_x0 + b;
+      emit(e[2], e[3], sqi, 0, mu, sigma);
+      if (e[4]) emit(e[4], e[5], sqi, 1, mu, sigma);
     }
   }
   *n_out = total;

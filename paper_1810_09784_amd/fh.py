@@ -239,15 +239,23 @@ def fh_device_errors(plan: Plan, stream=None) -> int:
 
 
 def fh_select(plan: Plan, hmap, sq_k: int, sq_x0: int, min_dk: int = 3, cr_thr: float = -1e300,
-              col_lo: int = 0, col_hi: int = 0, cap: int = 100000, stream=None):
-    """Candidates of a Hough map (list of dicts, square order)."""
+              col_lo: int = 0, col_hi: int = 0, cap: int = None, stream=None, as_dicts: bool = True):
+    """Candidates of a Hough map in square order: (list of dicts, total) or, with
+    as_dicts=False, (numpy structured array of the returned records, total).
+    cap defaults to 2 sq_k sq_x0, the most the selection can return."""
     assert hmap.is_cuda and tuple(hmap.shape) == (plan.n_k, plan.n_x0) and hmap.is_contiguous()
+    if cap is None:
+        cap = 2 * int(sq_k) * int(sq_x0)
     opts = SelectOpts(int(sq_k), int(sq_x0), int(min_dk), int(col_lo), int(col_hi), float(cr_thr))
     buf = (Candidate * max(1, cap))()
     n = C.c_int32()
     _check(lib().fh_select(plan.handle, C.c_void_p(_ptr(hmap)), C.byref(opts), buf, int(cap), C.byref(n),
                            _stream(stream)), "fh_select")
-    return [buf[i].as_dict() for i in range(min(n.value, cap))], int(n.value)
+    m = min(n.value, cap)
+    if not as_dicts:
+        import numpy as np
+        return np.ctypeslib.as_array(buf)[:m].copy(), int(n.value)
+    return [buf[i].as_dict() for i in range(m)], int(n.value)
 
 
 class Batch:

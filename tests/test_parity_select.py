@@ -78,6 +78,34 @@ def test_select_random_maps_with_ties(dev, oracle, seed):
     _compare(got, OS.select(ref_map, spec.k, x0m, dx, spec.n, sk, sx, 3))
 
 
+@pytest.mark.parametrize("n_x0,n_k,sq,cols,hi", [
+    (1001, 300, (300, 7), (3, 998), 3),      # one row per square, unaligned column range, many ties
+    (4099, 517, (1, 256), (1, 0), 100000),   # 517 rows in one square (strided row loop), 256 segments
+    (30001, 64, (5, 5), (0, 0), 50),         # long segments: the 4-deep 16-byte load loop and its tails
+    (37, 11, (11, 37), (0, 0), 2),           # one-column segments
+    (6, 3, (2, 2), (1, 6), 0),               # all-zero map: sigma = 0, no candidate
+])
+def test_select_random_integer_maps(dev, n_x0, n_k, sq, cols, hi):
+    # maps that fh_hough did not write: any counts, odd widths and column ranges
+    import torch
+    from paper_1810_09784_amd import fh
+    from oracle import select as OS
+    k = np.linspace(0.0, 1e-12, n_k)
+    plan = fh.Plan(3.0, 2.0, 100.0, 110.0, 4, k, x0_min=1e-4, dx0=1e-7, n_x0=n_x0)
+    g = torch.Generator(device=dev)
+    g.manual_seed(n_x0 * 7 + n_k)
+    H = torch.randint(0, hi + 1, (n_k, n_x0), generator=g, device=dev, dtype=torch.int32)
+    got, n = fh.fh_select(plan, H, sq[0], sq[1], 3, col_lo=cols[0], col_hi=cols[1])
+    ref = OS.select(H.cpu().numpy(), k, plan.info.x0_min, plan.info.dx0, 3.0, sq[0], sq[1], 3,
+                    col_lo=cols[0], col_hi=cols[1])
+    assert n == len(ref)
+    _compare(got, ref)
+    # a second call with fewer squares reuses the scratch
+    got2, _ = fh.fh_select(plan, H, 1, 1, 3, col_lo=cols[0], col_hi=cols[1])
+    _compare(got2, OS.select(H.cpu().numpy(), k, plan.info.x0_min, plan.info.dx0, 3.0, 1, 1, 3,
+                             col_lo=cols[0], col_hi=cols[1]))
+
+
 def test_large_map_full_parity_and_select(dev, oracle):
     # the whole 1024 x 84000 map against the oracle's, then 5 x 5 squares
     from paper_1810_09784_amd import fh
