@@ -67,18 +67,22 @@ __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirs
 // Drow points at the tile row (its slot at index c1 - c0 absorbs right edges
 // outside the tile); an empty or invalid interval sends both edges to the
 // lane's own discard word, so the update needs no branch.
-__device__ __forceinline__ void edge_update(int* Drow, int* discard, double C, double T, double a_lo, double a_hi,
+template <bool ZERO_COL>
+__device__ __forceinline__ void edge_update(int* Dcol, int* discard, double C, double T, double a_lo, double a_hi,
                                             int c0, int c1, bool valid) {
   const double u_lo = __builtin_fma(-C, T, a_lo);
   const double u_hi = __builtin_fma(-C, T, a_hi);
-  // max(floor(u), c0) == max(trunc(u), c0) for c0 >= 0; floor(u_hi) < 0 iff u_hi < 0
+  // max(floor(u), c0) == max(trunc(u), c0) for c0 >= 0.  floor(u_hi) < 0 iff
+  // u_hi < 0; trunc differs from floor there only on (-1, 0), which matters
+  // only when c0 == 0 (for c0 >= 1 such an interval already has hi < lo).
   const int lo = max(cvt_sat_i32(u_lo), c0);
   const int hi = min(cvt_sat_i32(u_hi), c1 - 1);
-  const bool ok = valid && !is_negative(u_hi) && lo <= hi;
-  int* plo = ok ? Drow + (lo - c0) : discard;
-  int* phi = ok ? Drow + (hi + 1 - c0) : discard;
+  const bool ok = valid && (!ZERO_COL || !is_negative(u_hi)) && lo <= hi;
+  // Dcol + c is column c of the tile row; the -1 lands one past Dcol[hi]
+  int* plo = ok ? Dcol + lo : discard;
+  int* phi = ok ? Dcol + hi : discard - 1;
   atomicAdd(plo, 1);
-  atomicAdd(phi, -1);
+  atomicAdd(phi + 1, -1);
 }
 
 // Global-memory views of the map's arrays (address space 1), so that loads
@@ -169,71 +173,38 @@ struct WaveScratch {
 };
 static_assert(sizeof(WaveScratch) == 1040, "per-wave LDS scratch size is part of the LDS budget");
 
-// One unit: tile `tile` of map M over FFTs [i_lo, i_hi); `atomic` when the
-// tile is split over several units (the map region was cleared beforehand).
-template <int THREADS, bool ALDS>
-__device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool atomic, bool load_a, char* smem) {
+// Shared state of one unit, set up by tile_body.
+struct TileCtx {
+  const double* A_s;      // A table in LDS (n_f + 2 entries) when ALDS
+  WaveScratch* wsc;       // per-wave scratch of the whole-FFT mode
+  const int* ia_s;        // per tile row: FFT range [ia, ib) that can reach the tile
+  const int* ib_s;
+  const int* flags;       // [0]: ib non-increasing over the rows, [1] [2]: union FFT range
+  int* discard;           // this lane's sink of empty intervals
+  int* D;                 // differential tile, rows x pitch
+  int rt, ct, r0, nrows, c0, c1, pitch, i_lo, i_hi, lane, wave;
+};
+
+// All (peak, row) pairs of a unit into the differential tile.  ZERO_COL: the
+// tile starts at column 0 (the only case that needs the sign test of u_hi).
+template <int THREADS, bool ALDS, bool ZERO_COL>
+__device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, const TileCtx& X) {
   constexpr int NW = THREADS / kWave;
-  const GMap G(M);
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wave = uniform(tid >> 6);
-
-  const int rt = tile / M.tiles_x;
-  const int ct = tile - rt * M.tiles_x;
-  const int r0 = rt * M.rows;
-  const int nrows = min(M.rows, M.n_k - r0);
-  const int c0 = ct * M.cols;
-  const int c1 = min(c0 + M.cols, M.n_x0);
-  const int W = c1 - c0;
-  const int pitch = M.pitch;
-
-  // LDS: [A (n_f+1) doubles][C rows doubles][wave scratch x NW][ia rows][ib rows][wtot 16][flags 4][D rows*pitch]
-  double* A_s = reinterpret_cast<double*>(smem);
-  double* C_s = A_s + (ALDS ? (M.n_f + 1) : 0);
-  WaveScratch* wsc = reinterpret_cast<WaveScratch*>(C_s + M.rows);
-  int* ia_s = reinterpret_cast<int*>(wsc + NW);
-  int* ib_s = ia_s + M.rows;
-  int* wtot = ib_s + M.rows;  // per-wave partial sums (16 ints)
-  int* flags = wtot + 16;     // [0]: ib non-increasing over the rows, [1] [2]: union FFT range
-  int* discard = flags + 4 + lane;  // per-lane sink of empty intervals (64 ints)
-  int* D = flags + 4 + kWave;
-
-  if (ALDS && load_a)
-    for (int j = tid; j <= M.n_f; j += THREADS) A_s[j] = G.A[j];
-  for (int x = tid; x < nrows * pitch; x += THREADS) D[x] = 0;
-  if (tid < nrows) {
-    const double C = G.C[r0 + tid];
-    C_s[tid] = C;
-    int a, b;
-    fft_range(M, G, C, c0, c1, i_lo, i_hi, &a, &b);
-    ia_s[tid] = a;
-    ib_s[tid] = b;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int mono = 1, lo = i_hi, hi = i_lo;
-    for (int r = 0; r < nrows; ++r) {
-      if (r > 0) mono &= ib_s[r] <= ib_s[r - 1];
-      if (ia_s[r] < ib_s[r]) {
-        lo = min(lo, ia_s[r]);
-        hi = max(hi, ib_s[r]);
-      }
-    }
-    flags[0] = mono;
-    flags[1] = lo;
-    flags[2] = hi;
-  }
-  __syncthreads();
-
+  const double* A_s = X.A_s;
+  const int* ia_s = X.ia_s;
+  const int* ib_s = X.ib_s;
+  int* discard = X.discard;
+  int* D = X.D;
+  const int rt = X.rt, ct = X.ct, r0 = X.r0, nrows = X.nrows, c0 = X.c0, c1 = X.c1, pitch = X.pitch;
+  const int i_lo = X.i_lo, i_hi = X.i_hi, lane = X.lane, wave = X.wave;
   if (M.mode == kModeWhole) {
     // Waves take blocks of 64 FFTs; lanes take the blocks' peaks 64 at a time
     // (coalesced) and loop over the tile rows that can reach the tile.
     const bool count_bad = (rt == 0 && ct == 0);  // each peak counted by one tile
-    const int mono = flags[0];
-    const int i_start = uniform(count_bad ? i_lo : flags[1]);
-    const int i_end = uniform(count_bad ? i_hi : max(flags[2], flags[1]));
-    WaveScratch& S = wsc[wave];
+    const int mono = X.flags[0];
+    const int i_start = uniform(count_bad ? i_lo : X.flags[1]);
+    const int i_end = uniform(count_bad ? i_hi : max(X.flags[2], X.flags[1]));
+    WaveScratch& S = X.wsc[wave];
     for (int f0 = i_start + wave * kWave; f0 < i_end; f0 += NW * kWave) {
       const int nb = min(kWave, i_end - f0);
       const int fi = f0 + min(lane, nb - 1);
@@ -271,14 +242,15 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
         const double T = S.T[u];
         const bool jv = pv && (unsigned)j < (unsigned)M.n_f;
         if (count_bad && pv && !jv) atomicAdd(M.err, 1ull);
-        const int jc = jv ? j : 0;
+        // a bad bin reads the pad entry A[n_f + 1] = +huge: an empty interval
+        const int jc = (int)min((unsigned)j, (unsigned)M.n_f);
         const double a_hi = ALDS ? A_s[jc] : G.A[jc];
         const double a_lo = ALDS ? A_s[jc + 1] : G.A[jc + 1];
         const int rbl = jv ? S.rb[u] : 0;
         const int rmax = wave_max(rbl);
         for (int r = 0; r < rmax; ++r) {
           const double C = G.C[r0 + r];  // uniform: a scalar load, no LDS ordering
-          edge_update(D + r * pitch, discard, C, T, a_lo, a_hi, c0, c1, r < rbl);
+          edge_update<ZERO_COL>(D + r * pitch - c0, discard, C, T, a_lo, a_hi, c0, c1, pv && r < rbl);
         }
       }
     }
@@ -288,7 +260,7 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
     for (int rl = 0; rl < nrows; ++rl) {
       const int ia = ia_s[rl], ib = ib_s[rl];
       const double C = G.C[r0 + rl];
-      int* Drow = D + rl * pitch;
+      int* Dcol = D + rl * pitch - c0;
       for (int qb = ia + wave * kWave; qb < ib; qb += NW * kWave) {
         const int i = qb + lane;
         const bool iv = i < ib;
@@ -338,18 +310,81 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
 #pragma unroll
             for (int e = 0; e < 4; ++e) {  // table reads of four peaks before their atomics
               const int q = g + 4 * h + e;
-              vv[e] = q >= pa && q < pe && (unsigned)jj[4 * h + e] < (unsigned)M.n_f;
-              const int jc = vv[e] ? jj[4 * h + e] : 0;
+              vv[e] = q >= pa && q < pe;
+              // a bad bin reads the pad entry A[n_f + 1] = +huge: an empty interval
+              const int jc = (int)min((unsigned)jj[4 * h + e], (unsigned)M.n_f);
               ahi[e] = ALDS ? A_s[jc] : G.A[jc];
               alo[e] = ALDS ? A_s[jc + 1] : G.A[jc + 1];
             }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) edge_update(Drow, discard, C, T, alo[e], ahi[e], c0, c1, vv[e]);
+            for (int e = 0; e < 4; ++e) edge_update<ZERO_COL>(Dcol, discard, C, T, alo[e], ahi[e], c0, c1, vv[e]);
           }
         }
       }
     }
   }
+}
+
+// One unit: tile `tile` of map M over FFTs [i_lo, i_hi); `atomic` when the
+// tile is split over several units (the map region was cleared beforehand).
+template <int THREADS, bool ALDS>
+__device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool atomic, bool load_a, char* smem) {
+  constexpr int NW = THREADS / kWave;
+  const GMap G(M);
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wave = uniform(tid >> 6);
+
+  const int rt = tile / M.tiles_x;
+  const int ct = tile - rt * M.tiles_x;
+  const int r0 = rt * M.rows;
+  const int nrows = min(M.rows, M.n_k - r0);
+  const int c0 = ct * M.cols;
+  const int c1 = min(c0 + M.cols, M.n_x0);
+  const int W = c1 - c0;
+  const int pitch = M.pitch;
+
+  // LDS: [A (n_f+2) doubles][C rows doubles][wave scratch x NW][ia rows][ib rows][wtot 16][flags 4][D rows*pitch]
+  double* A_s = reinterpret_cast<double*>(smem);
+  double* C_s = A_s + (ALDS ? (M.n_f + 2) : 0);
+  WaveScratch* wsc = reinterpret_cast<WaveScratch*>(C_s + M.rows);
+  int* ia_s = reinterpret_cast<int*>(wsc + NW);
+  int* ib_s = ia_s + M.rows;
+  int* wtot = ib_s + M.rows;  // per-wave partial sums (16 ints)
+  int* flags = wtot + 16;     // [0]: ib non-increasing over the rows, [1] [2]: union FFT range
+  int* discard = flags + 4 + lane;  // per-lane sink of empty intervals (64 ints)
+  int* D = flags + 4 + kWave;
+
+  if (ALDS && load_a)
+    for (int j = tid; j <= M.n_f + 1; j += THREADS) A_s[j] = G.A[j];
+  for (int x = tid; x < nrows * pitch; x += THREADS) D[x] = 0;
+  if (tid < nrows) {
+    const double C = G.C[r0 + tid];
+    C_s[tid] = C;
+    int a, b;
+    fft_range(M, G, C, c0, c1, i_lo, i_hi, &a, &b);
+    ia_s[tid] = a;
+    ib_s[tid] = b;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int mono = 1, lo = i_hi, hi = i_lo;
+    for (int r = 0; r < nrows; ++r) {
+      if (r > 0) mono &= ib_s[r] <= ib_s[r - 1];
+      if (ia_s[r] < ib_s[r]) {
+        lo = min(lo, ia_s[r]);
+        hi = max(hi, ib_s[r]);
+      }
+    }
+    flags[0] = mono;
+    flags[1] = lo;
+    flags[2] = hi;
+  }
+  __syncthreads();
+
+  const TileCtx X{A_s, wsc, ia_s, ib_s, flags, discard, D, rt, ct, r0, nrows, c0, c1, pitch, i_lo, i_hi, lane, wave};
+  if (c0 == 0) tile_pairs<THREADS, ALDS, true>(M, G, X);
+  else tile_pairs<THREADS, ALDS, false>(M, G, X);
   __syncthreads();
 
   // prefix sums along x0 and the store

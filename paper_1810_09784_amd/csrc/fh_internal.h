@@ -23,7 +23,7 @@ enum Mode : int32_t { kModeAuto = 0, kModeWhole = 1, kModeWindowed = 2 };
 
 // Everything a tile of one map needs, by value (kernel argument or table entry).
 struct MapArgs {
-  const double* A;         // [n_f + 1] column coordinate of each bin edge
+  const double* A;         // [n_f + 2] column coordinate of each bin edge, then a pad +huge
   const double* C;         // [n_k] column shift per second of each row
   const double* T;         // [n_fft] time of each FFT
   const int32_t* J;        // [n_J] last bin edge j with A_j >= c (windowed mode)

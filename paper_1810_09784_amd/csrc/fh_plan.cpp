@@ -29,7 +29,7 @@ int lds_bytes_for_shape(int n_f, int rows, int cols, int a_lds, int threads, int
   // [A][C rows][per-wave scratch 1040 B][ia, ib rows][16 + 4 ints][64 discard ints][D rows x pitch]
   long long b = (long long)rows * pitch * 4 + (long long)rows * 8 + (long long)(threads / 64) * 1040 +
                 (long long)rows * 8 + 80 + 16 + 256;
-  if (a_lds) b += (long long)(n_f + 1) * 8;
+  if (a_lds) b += (long long)(n_f + 2) * 8;
   return b > (1LL << 30) ? (1 << 30) : (int)b;
 }
 
@@ -409,7 +409,13 @@ extern "C" fh_status fh_plan(const fh_map_desc* d, const fh_tile_cfg* cfg, fh_pl
     p.unit_cost.swap(uc);
     p.grid = std::max(1, std::min<int>(resident, (int)p.units.size()));
   }
-  st = upload(&p.dA, p.A.data(), p.A.size());
+  {
+    // device A: the n_f + 1 bin edges and a pad entry +huge, read for a bad bin
+    // (its interval is then empty)
+    std::vector<double> a_pad(p.A);
+    a_pad.push_back(1e300);
+    st = upload(&p.dA, a_pad.data(), a_pad.size());
+  }
   if (st == FH_OK) st = upload(&p.dC, p.C.data(), p.C.size());
   if (st == FH_OK) st = upload(&p.dT, p.T.data(), p.T.size());
   if (st == FH_OK && p.n_J > 0) st = upload(&p.dJ, p.J.data(), p.J.size());
