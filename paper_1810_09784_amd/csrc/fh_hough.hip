@@ -173,6 +173,68 @@ struct WaveScratch {
 };
 static_assert(sizeof(WaveScratch) == 1040, "per-wave LDS scratch size is part of the LDS budget");
 
+// Epilogue helpers.  A tile row of the differential D is read in chunks of 4
+// columns (16-byte LDS accesses); pitch is a multiple of 4 and covers the pad
+// column W, so every chunk of a row lies inside it.
+
+// Sum of chunks [k0, k1) of a D row over the wave's lanes (result per lane).
+__device__ __forceinline__ int sum_chunks(const int* Drow, int k0, int k1, int lane) {
+  int s = 0;
+#pragma unroll 4
+  for (int kb = k0; kb < k1; kb += kWave) {
+    const int k = kb + lane;
+    const v4i v = *reinterpret_cast<const v4i*>(Drow + 4 * min(k, k1 - 1));
+    s += k < k1 ? (v.x + v.y) + (v.z + v.w) : 0;
+  }
+  return s;
+}
+
+// Inclusive prefix sums of chunks [k0, k1) of a D row on top of `carry`:
+// columns below W go to `out`, and every chunk is left zero for the next
+// unit.  Plain stores go out as 16-byte chunks when `vec`; atomic adds (split
+// tiles) go through the row in LDS so that each instruction covers 64
+// consecutive columns.  Returns the carry after the last chunk.
+__device__ __forceinline__ int scan_chunks(int* Drow, int k0, int k1, int carry, int W, gptr<int> out, bool vec,
+                                           bool atomic, int lane) {
+  for (int kb = k0; kb < k1; kb += kWave) {
+    const int k = kb + lane;
+    const bool in = k < k1;
+    v4i* slot = reinterpret_cast<v4i*>(Drow + 4 * min(k, k1 - 1));
+    v4i v = *slot;
+    if (!in) v = v4i{0, 0, 0, 0};
+    v.y += v.x;
+    v.z += v.y;
+    v.w += v.z;
+    const int incl = wave_incl_scan(v.w);
+    v += carry + incl - v.w;
+    if (in) {
+      const int c = 4 * k;
+      if (atomic) {
+        *slot = v;  // the counts, for the column pass below
+      } else {
+        *slot = v4i{0, 0, 0, 0};
+        if (vec && c + 3 < W) {
+          *(gptr<v4i>)(out + c) = v;
+        } else {
+          if (c < W) out[c] = v.x;
+          if (c + 1 < W) out[c + 1] = v.y;
+          if (c + 2 < W) out[c + 2] = v.z;
+          if (c + 3 < W) out[c + 3] = v.w;
+        }
+      }
+    }
+    carry += __builtin_amdgcn_readlane(incl, 63);
+  }
+  if (atomic) {  // this wave's own columns, in order (LDS is in order within a wave)
+    for (int x = 4 * k0 + lane; x < 4 * k1; x += kWave) {
+      const int y = Drow[x];
+      Drow[x] = 0;
+      if (x < W && y) __hip_atomic_fetch_add(out + x, y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  return carry;
+}
+
 // Shared state of one unit, set up by tile_body.
 struct TileCtx {
   const double* A_s;      // A table in LDS (n_f + 2 entries) when ALDS
@@ -327,8 +389,11 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
 
 // One unit: tile `tile` of map M over FFTs [i_lo, i_hi); `atomic` when the
 // tile is split over several units (the map region was cleared beforehand).
+// `clean`: leading words of the differential tile at LDS offset `clean_at`
+// known to be zero (each epilogue leaves the rows it used zero).
 template <int THREADS, bool ALDS>
-__device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool atomic, bool load_a, char* smem) {
+__device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool atomic, bool load_a, char* smem,
+                          int& clean, int& clean_at) {
   constexpr int NW = THREADS / kWave;
   const GMap G(M);
   const int tid = threadIdx.x;
@@ -344,7 +409,8 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
   const int W = c1 - c0;
   const int pitch = M.pitch;
 
-  // LDS: [A (n_f+2) doubles][C rows doubles][wave scratch x NW][ia rows][ib rows][wtot 16][flags 4][D rows*pitch]
+  // LDS: [A (n_f+2) doubles][C rows doubles][wave scratch x NW][ia rows][ib rows][wtot 16][flags 4][discard 64]
+  //      [D rows*pitch, 16-byte aligned]
   double* A_s = reinterpret_cast<double*>(smem);
   double* C_s = A_s + (ALDS ? (M.n_f + 2) : 0);
   WaveScratch* wsc = reinterpret_cast<WaveScratch*>(C_s + M.rows);
@@ -353,11 +419,13 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
   int* wtot = ib_s + M.rows;  // per-wave partial sums (16 ints)
   int* flags = wtot + 16;     // [0]: ib non-increasing over the rows, [1] [2]: union FFT range
   int* discard = flags + 4 + lane;  // per-lane sink of empty intervals (64 ints)
-  int* D = flags + 4 + kWave;
+  const int d_at = ((int)(reinterpret_cast<char*>(flags + 4 + kWave) - smem) + 15) & ~15;
+  int* D = reinterpret_cast<int*>(smem + d_at);
 
   if (ALDS && load_a)
     for (int j = tid; j <= M.n_f + 1; j += THREADS) A_s[j] = G.A[j];
-  for (int x = tid; x < nrows * pitch; x += THREADS) D[x] = 0;
+  if (clean_at != d_at || clean < nrows * pitch)
+    for (int x = tid; x < nrows * pitch; x += THREADS) D[x] = 0;
   if (tid < nrows) {
     const double C = G.C[r0 + tid];
     C_s[tid] = C;
@@ -387,59 +455,33 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
   else tile_pairs<THREADS, ALDS, false>(M, G, X);
   __syncthreads();
 
-  // prefix sums along x0 and the store
+  // prefix sums along x0 and the store; D is left zero
+  const int P4 = pitch >> 2;
   if (nrows >= NW) {
     for (int rl = wave; rl < nrows; rl += NW) {
-      const int* Drow = D + rl * pitch;
       gptr<int> out = G.map + (size_t)(r0 + rl) * M.n_x0 + c0;
-      int carry = 0;
-      for (int x0 = 0; x0 < W; x0 += kWave) {
-        const int x = x0 + lane;
-        const int v = x < W ? Drow[x] : 0;
-        const int s = wave_incl_scan(v) + carry;
-        if (x < W) {
-          if (atomic) {
-            if (s) __hip_atomic_fetch_add(out + x, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          } else {
-            out[x] = s;
-          }
-        }
-        carry = __builtin_amdgcn_readlane(s, 63);
-      }
+      const bool vec = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+      scan_chunks(D + rl * pitch, 0, P4, 0, W, out, vec, atomic, lane);
     }
   } else {
-    // few rows: all waves share each row, one segment per wave
-    const int seg = ((W + NW - 1) / NW + kWave - 1) / kWave * kWave;
+    // few rows: all waves share each row, one run of chunks per wave
+    const int segc = (P4 + NW - 1) / NW;
+    const int k0 = min(wave * segc, P4), k1 = min(k0 + segc, P4);
     for (int rl = 0; rl < nrows; ++rl) {
-      const int* Drow = D + rl * pitch;
-      const int xs = wave * seg, xe = min(W, xs + seg);
-      int part = 0;
-      for (int x0 = xs; x0 < xe; x0 += kWave) {
-        const int x = x0 + lane;
-        part += x < xe ? Drow[x] : 0;
-      }
-      part = wave_incl_scan(part);
+      int* Drow = D + rl * pitch;
+      const int part = wave_incl_scan(sum_chunks(Drow, k0, k1, lane));
       if (lane == 63) wtot[wave] = part;
       __syncthreads();
       int carry = 0;
       for (int w = 0; w < wave; ++w) carry += wtot[w];
       gptr<int> out = G.map + (size_t)(r0 + rl) * M.n_x0 + c0;
-      for (int x0 = xs; x0 < xe; x0 += kWave) {
-        const int x = x0 + lane;
-        const int v = x < xe ? Drow[x] : 0;
-        const int s = wave_incl_scan(v) + carry;
-        if (x < xe) {
-          if (atomic) {
-            if (s) __hip_atomic_fetch_add(out + x, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          } else {
-            out[x] = s;
-          }
-        }
-        carry = __builtin_amdgcn_readlane(s, 63);
-      }
+      const bool vec = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
+      scan_chunks(Drow, k0, k1, carry, W, out, vec, atomic, lane);
       __syncthreads();
     }
   }
+  clean = nrows * pitch;
+  clean_at = d_at;
 }
 
 // Persistent work-queue kernel: work-groups claim units (ordered longest
@@ -451,6 +493,7 @@ __global__ void __launch_bounds__(THREADS) k_queue(MapArgs M0, const MapArgs* __
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_item;
   int loaded = -1;  // map whose A table is in LDS
+  int clean = 0, clean_at = -1;  // zero part of the differential tile
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(head, 1);
     __syncthreads();
@@ -461,9 +504,9 @@ __global__ void __launch_bounds__(THREADS) k_queue(MapArgs M0, const MapArgs* __
     const int mi = u.x & ~kUnitAtomic;
     if (maps) {
       const MapArgs M = maps[mi];
-      tile_body<THREADS, ALDS>(M, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem);
+      tile_body<THREADS, ALDS>(M, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem, clean, clean_at);
     } else {
-      tile_body<THREADS, ALDS>(M0, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem);
+      tile_body<THREADS, ALDS>(M0, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem, clean, clean_at);
     }
     loaded = mi;
     __syncthreads();

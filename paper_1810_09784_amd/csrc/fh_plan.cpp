@@ -26,9 +26,9 @@ static int round_up(int x, int m) { return (x + m - 1) / m * m; }
 int lds_bytes_for_shape(int n_f, int rows, int cols, int a_lds, int threads, int* pitch_out) {
   int pitch = round_up(cols + 1, 4);
   if (pitch_out) *pitch_out = pitch;
-  // [A][C rows][per-wave scratch 1040 B][ia, ib rows][16 + 4 ints][64 discard ints][D rows x pitch]
+  // [A][C rows][per-wave scratch 1040 B][ia, ib rows][16 + 4 ints][64 discard ints][D rows x pitch, 16-aligned]
   long long b = (long long)rows * pitch * 4 + (long long)rows * 8 + (long long)(threads / 64) * 1040 +
-                (long long)rows * 8 + 80 + 16 + 256;
+                (long long)rows * 8 + 80 + 16 + 256 + 16;
   if (a_lds) b += (long long)(n_f + 2) * 8;
   return b > (1LL << 30) ? (1 << 30) : (int)b;
 }
