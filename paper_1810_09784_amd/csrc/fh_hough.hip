@@ -235,6 +235,8 @@ __device__ __forceinline__ int scan_chunks(int* Drow, int k0, int k1, int carry,
   return carry;
 }
 
+constexpr int kWinQuads = 2;  // windowed mode: 16-byte bin groups per loop step (8 peaks)
+
 // Shared state of one unit, set up by tile_body.
 struct TileCtx {
   const double* A_s;      // A table in LDS (n_f + 2 entries) when ALDS
@@ -348,11 +350,11 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
           pa = min(base + peak_rank(M, G, ic, ja), end);
           pe = max(min(base + peak_rank(M, G, ic, jb + 1), end), pa);
         }
-        // 16-byte aligned groups of four bins, four groups in flight per lane
-        for (int g = pa & ~3; g < pe; g += 16) {
-          int jj[16];
+        // 16-byte aligned groups of four bins, kWinQuads groups per step
+        for (int g = pa & ~3; g < pe; g += 4 * kWinQuads) {
+          int jj[4 * kWinQuads];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) {
+          for (int k = 0; k < kWinQuads; ++k) {
             const int q = g + 4 * k;
             if (q + 3 < M.n_peaks && q < pe) {
               const v4i v = *(gptr<const v4i>)(G.bin + q);
@@ -366,7 +368,7 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
             }
           }
 #pragma unroll
-          for (int h = 0; h < 4; ++h) {
+          for (int h = 0; h < kWinQuads; ++h) {
             double alo[4], ahi[4];
             bool vv[4];
 #pragma unroll
