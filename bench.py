@@ -6,7 +6,10 @@ Workload: the large single map (n = 3, 200-1200 Hz, T_FFT = 4 s, 43200 FFTs =
 Exp(1) noise with 20 injections).  One step = the whole hot path on that
 peakmap, inputs resident in HBM: peak ingest (rank structure), the Hough
 transform into the differential LDS tiles, the prefix sums and the map store
-(fh_hough), then candidate selection when the library provides it.
+(fh_hough), then candidate selection (fh_select).  The timed steps are
+pipelined: step k's transform (one stream) overlaps step k-1's selection (a
+second stream, reading the other of two map buffers); the serial step time is
+reported beside it.
 
 Metric: FH Hough updates/s, an update being one (peak, k-row) pair, counted
 over all P * n_k pairs.  Also reported: the batched persistent launch over the
@@ -123,35 +126,60 @@ def main():
         e0.record(stream)
         e1.record(stream)
     torch.cuda.synchronize()
-    state = {"k": -1}
-
     cands = {}
 
-    def step():
-        i = state["k"]
-        if 0 <= i < K:
-            fh.fh_plan_set_events(plan, ev[i][0], ev[i][1])
-        else:
-            fh.fh_plan_set_events(plan, None, None)
-        fh.fh_hough(plan, rp, bn, hmap, stream)
+    def select(m, st):
         # candidate selection: 5 x 5 squares, a second candidate >= 3 k rows away (Sec. IV)
-        cands["list"], cands["n"] = fh.fh_select(plan, hmap, 5, 5, 3, stream=stream, as_dicts=False)
-        if i >= 0:
-            state["k"] = i + 1
+        cands["list"], cands["n"] = fh.fh_select(plan, m, 5, 5, 3, stream=st, as_dicts=False)
 
-    for _ in range(W):
-        step()
+    # (1) serial steps: fh_hough then fh_select on one stream, the host waiting for each step
+    def serial_step():
+        fh.fh_hough(plan, rp, bn, hmap, stream)
+        select(hmap, stream)
+
+    ms_serial, _ = timed_steps(serial_step, K, W, stream)
+    # the Hough transform alone (rank build + tiles), same launch configuration
+    ms_hough, _ = timed_steps(lambda: fh.fh_hough(plan, rp, bn, hmap, stream), K, 2, stream)
+
+    # (2) the timed run: steps pipelined over two map buffers and two streams.  Step k's
+    # fh_hough (stream A) runs while step k-1's fh_select (stream B, after A's event for
+    # that map) reads the other buffer, so the selection kernels and the host's part of
+    # the selection overlap the next transform.  Every step does the whole hot path.
+    sel_stream = torch.cuda.Stream()
+    hmaps = [hmap, torch.empty_like(hmap)]
+    done = [torch.cuda.Event(), torch.cuda.Event()]
+
+    def pipelined(n, timed):
+        for k in range(n):
+            j = k & 1
+            if timed:
+                fh.fh_plan_set_events(plan, ev[k][0], ev[k][1])
+            fh.fh_hough(plan, rp, bn, hmaps[j], stream)
+            done[j].record(stream)
+            if k > 0:
+                sel_stream.wait_event(done[1 - j])
+                select(hmaps[1 - j], sel_stream)
+        sel_stream.wait_event(done[(n - 1) & 1])
+        select(hmaps[(n - 1) & 1], sel_stream)
+        fh.fh_plan_set_events(plan, None, None)
+
+    pipelined(W, False)
     torch.cuda.synchronize()
-    state["k"] = 0
-    ms, wall = timed_steps(step, K, 0, stream)
-    fh.fh_plan_set_events(plan, None, None)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    wall0 = time.perf_counter()
+    pipelined(K, True)
+    t1.record(sel_stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1) / K
     kern_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / K
     errs = fh.fh_device_errors(plan)
     assert errs == 0, f"{errs} bad peaks"
-    log(f"step {ms:.4f} ms (host wall {wall / K * 1e3:.4f} ms), hough tile kernel {kern_ms:.4f} ms, "
-        f"{cands['n']} candidates")
-    # the Hough transform alone (rank build + tiles), same launch configuration
-    ms_hough, _ = timed_steps(lambda: fh.fh_hough(plan, rp, bn, hmap, stream), K, 2, stream)
+    hmap = hmaps[(K - 1) & 1]  # the last step's map, checked against the oracle below
+    log(f"step {ms:.4f} ms pipelined (host wall {wall / K * 1e3:.4f} ms), {ms_serial:.4f} ms serial; "
+        f"hough {ms_hough:.4f} ms, tile kernel {kern_ms:.4f} ms, {cands['n']} candidates")
 
     # roofline of the tile kernel: algorithmic bytes = map store + peaks + CSR + tables, once
     map_bytes = 4 * plan.n_k * plan.n_x0
@@ -180,9 +208,11 @@ def main():
         "config": {"workload": "single map n=3, 200-1200 Hz, T_FFT=4 s, 43200 FFTs, 1024 k x 84000 x0",
                    "peaks": pm.n_peaks, "n_k": plan.n_k, "n_x0": plan.n_x0, "updates_per_step": U,
                    "tile": plan.tile, "parallelism": "1 GPU",
-                   "step": "fh_hough (rank build + tile kernel) + fh_select (5x5 squares, 2nd >= 3 rows)"},
-        "stages_ms": {"hough": round(ms_hough, 5), "hough_tile_kernel": round(kern_ms, 5),
-                      "select_incl_host": round(ms - ms_hough, 5)},
+                   "step": "fh_hough (rank build + tile kernel) + fh_select (5x5 squares, 2nd >= 3 rows), "
+                           "steps pipelined over two map buffers and two streams"},
+        "stages_ms": {"step_serial": round(ms_serial, 5), "hough": round(ms_hough, 5),
+                      "hough_tile_kernel": round(kern_ms, 5), "select_incl_host_serial": round(ms_serial - ms_hough, 5)},
+        "step_serial_updates_per_s": U / (ms_serial * 1e-3),
         "hough_only_updates_per_s": U / (ms_hough * 1e-3),
         "roofline": roof,
     }

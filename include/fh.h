@@ -20,7 +20,10 @@
  *     owned by the caller.  Host pointers are read during the call only.
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
  *     Calls that take a stream are asynchronous on it unless stated.
- *   - A plan may be used from one stream at a time (it owns scratch).
+ *   - A plan owns scratch: its fh_hough calls (and the batches holding it) run
+ *     one at a time, on one stream at a time; its fh_select calls likewise.
+ *     The two kinds use separate scratch, so a selection of one map may run
+ *     on another stream while the plan transforms the next map.
  *
  * The peak bin b of FFT i stands for the frequency bin [f_min + b df,
  * f_min + (b+1) df), df = 1/tfft.  Its x-image is shifted, at row r and time

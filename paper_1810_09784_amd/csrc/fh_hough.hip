@@ -516,9 +516,12 @@ __global__ void __launch_bounds__(THREADS) k_queue(MapArgs M0, const MapArgs* __
 }
 
 // Before a launch: queue head and error words to zero, split tiles cleared.
+// Grid: (clears, kClearSplit); block y clears its share of the columns of
+// every row of the tile.
+constexpr int kClearSplit = 8;
 __global__ void k_prologue(MapArgs M0, const MapArgs* __restrict__ maps, int n_maps, const int4* __restrict__ clears,
                            int n_clears, int* head) {
-  if (blockIdx.x == 0) {
+  if (blockIdx.x == 0 && blockIdx.y == 0) {
     if (threadIdx.x == 0) *head = 0;
     for (int m = threadIdx.x; m < n_maps; m += blockDim.x) *(maps ? maps[m].err : M0.err) = 0;
   }
@@ -528,9 +531,11 @@ __global__ void k_prologue(MapArgs M0, const MapArgs* __restrict__ maps, int n_m
     const int rt = e.y / M.tiles_x, ct = e.y % M.tiles_x;
     const int r0 = rt * M.rows, nrows = min(M.rows, M.n_k - r0);
     const int c0 = ct * M.cols, W = min(M.cols, M.n_x0 - c0);
-    for (int x = threadIdx.x; x < nrows * W; x += blockDim.x) {
-      const int r = x / W, col = x - r * W;
-      M.map[(size_t)(r0 + r) * M.n_x0 + c0 + col] = 0;
+    const int per = (W + (int)gridDim.y - 1) / (int)gridDim.y;
+    const int xa = (int)blockIdx.y * per, xb = min(W, xa + per);
+    for (int r = 0; r < nrows; ++r) {
+      gptr<int> row = (gptr<int>)M.map + (size_t)(r0 + r) * M.n_x0 + c0;
+      for (int x = xa + (int)threadIdx.x; x < xb; x += blockDim.x) row[x] = 0;
     }
   }
 }
@@ -546,7 +551,8 @@ __global__ void k_prologue(MapArgs M0, const MapArgs* __restrict__ maps, int n_m
 // than the LDS holds take the per-(FFT, word) binary search instead.
 constexpr int kPrepWaves = 8;
 constexpr int kPrepMaxWords = 512;
-constexpr int kPrepLdsWords = 16384;  // 64 KB of dynamic LDS per work-group
+constexpr int kPrepLdsWords = 10240;  // 40 KB of dynamic LDS per work-group (four per CU)
+constexpr int kPrepUnroll = 8;        // peaks per lane loaded ahead (512 per wavefront step)
 
 // FFTs per group: the largest power of two <= 64 whose entries (row pitch
 // F + 1 u64) fit beside the waves' scratch.
@@ -568,21 +574,31 @@ __device__ void prepare_fft_lds(const MapArgs& M, int i, int lane, unsigned* cnt
   wave_sync_lds();
   int bad = 0, neg = 0;
   int last = INT_MIN;  // bin of the previous peak of this FFT
-  for (int p0 = lo; p0 < hi; p0 += kWave) {
-    const int p = p0 + lane;
-    const bool v = p < hi;
-    const int j = v ? G.bin[p] : 0;
-    int jm = __shfl_up(j, 1);
-    if (lane == 0) jm = last;
-    last = __shfl(j, kWave - 1);
-    if (v) {
-      bad += j <= jm;  // not ascending
-      if (j < 0 || j >= M.n_f) {
-        ++bad;
-        neg += j < 0;
-      } else {
-        atomicAdd(&cnt[j >> 5], 1u);
-        atomicOr(&msk[j >> 5], 1u << (j & 31));
+  for (int p0 = lo; p0 < hi; p0 += kPrepUnroll * kWave) {
+    int jv[kPrepUnroll];  // all loads of the step in flight before the first use
+#pragma unroll
+    for (int u = 0; u < kPrepUnroll; ++u) {
+      const int p = p0 + u * kWave + lane;
+      jv[u] = p < hi ? G.bin[p] : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPrepUnroll; ++u) {
+      if (p0 + u * kWave >= hi) break;
+      const int p = p0 + u * kWave + lane;
+      const bool v = p < hi;
+      const int j = jv[u];
+      int jm = __shfl_up(j, 1);
+      if (lane == 0) jm = last;
+      last = __shfl(j, kWave - 1);
+      if (v) {
+        bad += j <= jm;  // not ascending
+        if (j < 0 || j >= M.n_f) {
+          ++bad;
+          neg += j < 0;
+        } else {
+          atomicAdd(&cnt[j >> 5], 1u);
+          atomicOr(&msk[j >> 5], 1u << (j & 31));
+        }
       }
     }
   }
@@ -645,7 +661,8 @@ __device__ void prepare_map(const MapArgs& M, unsigned* lds) {
     for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
       const int i0 = g * F;
       const int nf = min(F, M.n_fft - i0);
-      for (int f = wave; f < nf; f += kPrepWaves) prepare_fft_lds(M, i0 + f, lane, cnt, cnt + M.n_words, rbuf + f, pitch);
+      for (int f = wave; f < nf; f += kPrepWaves)
+        prepare_fft_lds(M, uniform(i0 + f), lane, cnt, cnt + M.n_words, rbuf + f, pitch);
       __syncthreads();
       const int n = M.n_words * F;
       for (int e = threadIdx.x; e < n; e += blockDim.x) {
@@ -708,7 +725,7 @@ fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStrea
   MapArgs a = p.args(pk, map);
   if (p.units.empty()) return FH_EINVAL;
   const int n_clears = (int)p.clears.size();
-  hipLaunchKernelGGL(k_prologue, dim3((unsigned)std::max(1, std::min(n_clears, 1024))), dim3(256), 0, s, a,
+  hipLaunchKernelGGL(k_prologue, dim3((unsigned)std::max(1, std::min(n_clears, 1024)), kClearSplit), dim3(256), 0, s, a,
                      (const MapArgs*)nullptr, 1, (const int4*)p.dClears, n_clears, p.dHead);
   if (check_launch() != FH_OK) return FH_EDEVICE;
   if (a.mode == kModeWindowed) {
@@ -837,7 +854,8 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
   MapArgs none{};
   bool ok = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
-    hipLaunchKernelGGL(k_prologue, dim3((unsigned)std::max(1, std::min(b->n_clears, 1024))), dim3(256), 0, b->cap,
+    hipLaunchKernelGGL(k_prologue, dim3((unsigned)std::max(1, std::min(b->n_clears, 1024)), kClearSplit), dim3(256), 0,
+                       b->cap,
                        none, (const MapArgs*)b->d_maps, m, (const int4*)b->d_clears, b->n_clears, b->d_head);
     if (any_windowed)
       hipLaunchKernelGGL(k_prepare_batch, dim3(2048), dim3(kPrepWaves * 64), kPrepLdsWords * 4, b->cap, b->d_maps,
