@@ -63,6 +63,14 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
 
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// x of lane `l` (wave-uniform) as a double.
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // One (peak, row) pair: the +1/-1 edges of its clipped interval in the tile.
 // Drow points at the tile row (its slot at index c1 - c0 absorbs right edges
 // outside the tile); an empty or invalid interval sends both edges to the
@@ -269,6 +277,9 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
     const int i_start = uniform(count_bad ? i_lo : X.flags[1]);
     const int i_end = uniform(count_bad ? i_hi : max(X.flags[2], X.flags[1]));
     WaveScratch& S = X.wsc[wave];
+    // C of tile row `lane` in each lane (rows <= 64): the row loop broadcasts it
+    // with v_readlane instead of a memory load per row
+    const double C_lane = G.C[r0 + min(lane, nrows - 1)];
     for (int f0 = i_start + wave * kWave; f0 < i_end; f0 += NW * kWave) {
       const int nb = min(kWave, i_end - f0);
       const int fi = f0 + min(lane, nb - 1);
@@ -313,7 +324,7 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
         const int rbl = jv ? S.rb[u] : 0;
         const int rmax = wave_max(rbl);
         for (int r = 0; r < rmax; ++r) {
-          const double C = G.C[r0 + r];  // uniform: a scalar load, no LDS ordering
+          const double C = readlane_f64(C_lane, r);
           edge_update<ZERO_COL>(D + r * pitch - c0, discard, C, T, a_lo, a_hi, c0, c1, pv && r < rbl);
         }
       }
