@@ -259,7 +259,9 @@ struct TileCtx {
 
 // All (peak, row) pairs of a unit into the differential tile.  ZERO_COL: the
 // tile starts at column 0 (the only case that needs the sign test of u_hi).
-template <int THREADS, bool ALDS, bool ZERO_COL>
+// MODE: kModeWhole or kModeWindowed compiles only that path; 0 takes the
+// map's mode at run time (batches of mixed maps).
+template <int THREADS, bool ALDS, int MODE, bool ZERO_COL>
 __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, const TileCtx& X) {
   constexpr int NW = THREADS / kWave;
   const double* A_s = X.A_s;
@@ -269,7 +271,7 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
   int* D = X.D;
   const int rt = X.rt, ct = X.ct, r0 = X.r0, nrows = X.nrows, c0 = X.c0, c1 = X.c1, pitch = X.pitch;
   const int i_lo = X.i_lo, i_hi = X.i_hi, lane = X.lane, wave = X.wave;
-  if (M.mode == kModeWhole) {
+  if (MODE == 0 ? M.mode == kModeWhole : MODE == kModeWhole) {
     // Waves take blocks of 64 FFTs; lanes take the blocks' peaks 64 at a time
     // (coalesced) and loop over the tile rows that can reach the tile.
     const bool count_bad = (rt == 0 && ct == 0);  // each peak counted by one tile
@@ -404,7 +406,7 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
 // tile is split over several units (the map region was cleared beforehand).
 // `clean`: leading words of the differential tile at LDS offset `clean_at`
 // known to be zero (each epilogue leaves the rows it used zero).
-template <int THREADS, bool ALDS>
+template <int THREADS, bool ALDS, int MODE>
 __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool atomic, bool load_a, char* smem,
                           int& clean, int& clean_at) {
   constexpr int NW = THREADS / kWave;
@@ -464,8 +466,8 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
   __syncthreads();
 
   const TileCtx X{A_s, wsc, ia_s, ib_s, flags, discard, D, rt, ct, r0, nrows, c0, c1, pitch, i_lo, i_hi, lane, wave};
-  if (c0 == 0) tile_pairs<THREADS, ALDS, true>(M, G, X);
-  else tile_pairs<THREADS, ALDS, false>(M, G, X);
+  if (c0 == 0) tile_pairs<THREADS, ALDS, MODE, true>(M, G, X);
+  else tile_pairs<THREADS, ALDS, MODE, false>(M, G, X);
   __syncthreads();
 
   // prefix sums along x0 and the store; D is left zero
@@ -500,7 +502,7 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
 // Persistent work-queue kernel: work-groups claim units (ordered longest
 // first) through an atomic counter until the queue is empty.  maps == nullptr:
 // every unit belongs to M0.
-template <int THREADS, bool ALDS>
+template <int THREADS, bool ALDS, int MODE>
 __global__ void __launch_bounds__(THREADS) k_queue(MapArgs M0, const MapArgs* __restrict__ maps,
                                                   const Unit* __restrict__ units, int n_units, int* head) {
   extern __shared__ __align__(16) char smem[];
@@ -517,9 +519,10 @@ __global__ void __launch_bounds__(THREADS) k_queue(MapArgs M0, const MapArgs* __
     const int mi = u.x & ~kUnitAtomic;
     if (maps) {
       const MapArgs M = maps[mi];
-      tile_body<THREADS, ALDS>(M, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem, clean, clean_at);
+      tile_body<THREADS, ALDS, MODE>(M, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem, clean, clean_at);
     } else {
-      tile_body<THREADS, ALDS>(M0, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem, clean, clean_at);
+      tile_body<THREADS, ALDS, MODE>(M0, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem, clean,
+                                     clean_at);
     }
     loaded = mi;
     __syncthreads();
@@ -705,18 +708,25 @@ __global__ void __launch_bounds__(kPrepWaves * 64) k_prepare_batch(const MapArgs
 
 static fh_status check_launch() { return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE; }
 
-template <int THREADS, bool ALDS>
+template <int THREADS, bool ALDS, int MODE>
 static void set_lds_attr(int lds) {
   if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute((const void*)k_queue<THREADS, ALDS>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    (void)hipFuncSetAttribute((const void*)k_queue<THREADS, ALDS, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              lds);
 }
 
-int occupancy_grid(int threads, int lds_bytes, int n_units) {
+template <int MODE>
+static const void* queue_fn(int threads) {
+  return threads == 1024 ? (const void*)k_queue<1024, true, MODE>
+         : threads == 512 ? (const void*)k_queue<512, true, MODE> : (const void*)k_queue<256, true, MODE>;
+}
+
+int occupancy_grid(int threads, int lds_bytes, int n_units, int mode) {
   int per_cu = 0, dev = 0, cus = 0;
   (void)hipGetDevice(&dev);
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-  const void* fn = threads == 1024 ? (const void*)k_queue<1024, true>
-                   : threads == 512 ? (const void*)k_queue<512, true> : (const void*)k_queue<256, true>;
+  const void* fn = mode == kModeWhole ? queue_fn<kModeWhole>(threads)
+                   : mode == kModeWindowed ? queue_fn<kModeWindowed>(threads) : queue_fn<0>(threads);
   if (lds_bytes > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds_bytes) != hipSuccess || per_cu < 1)
     per_cu = 1;
@@ -724,12 +734,20 @@ int occupancy_grid(int threads, int lds_bytes, int n_units) {
   return (int)std::min<long long>(g, std::max(n_units, 1));
 }
 
-template <int THREADS, bool ALDS>
+template <int THREADS, bool ALDS, int MODE>
 static fh_status launch_queue(const MapArgs& a, const Plan& p, hipStream_t s) {
-  set_lds_attr<THREADS, ALDS>(a.lds_bytes);
-  hipLaunchKernelGGL((k_queue<THREADS, ALDS>), dim3((unsigned)p.grid), dim3(THREADS), a.lds_bytes, s, a,
+  set_lds_attr<THREADS, ALDS, MODE>(a.lds_bytes);
+  hipLaunchKernelGGL((k_queue<THREADS, ALDS, MODE>), dim3((unsigned)p.grid), dim3(THREADS), a.lds_bytes, s, a,
                      (const MapArgs*)nullptr, (const Unit*)p.dUnits, (int)p.units.size(), p.dHead);
   return check_launch();
+}
+
+template <int MODE>
+static fh_status launch_queue_mode(const MapArgs& a, const Plan& p, hipStream_t s) {
+  const int th = p.tile.threads;
+  if (th == 1024) return a.a_lds ? launch_queue<1024, true, MODE>(a, p, s) : launch_queue<1024, false, MODE>(a, p, s);
+  if (th == 512) return a.a_lds ? launch_queue<512, true, MODE>(a, p, s) : launch_queue<512, false, MODE>(a, p, s);
+  return a.a_lds ? launch_queue<256, true, MODE>(a, p, s) : launch_queue<256, false, MODE>(a, p, s);
 }
 
 fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStream_t s) {
@@ -743,12 +761,9 @@ fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStrea
     hipLaunchKernelGGL(k_prepare, dim3(2048), dim3(kPrepWaves * 64), kPrepLdsWords * 4, s, a);
     if (check_launch() != FH_OK) return FH_EDEVICE;
   }
-  const int th = p.tile.threads;
   if (p.ev_start && hipEventRecord(p.ev_start, s) != hipSuccess) return FH_EDEVICE;
-  fh_status st;
-  if (th == 1024) st = a.a_lds ? launch_queue<1024, true>(a, p, s) : launch_queue<1024, false>(a, p, s);
-  else if (th == 512) st = a.a_lds ? launch_queue<512, true>(a, p, s) : launch_queue<512, false>(a, p, s);
-  else st = a.a_lds ? launch_queue<256, true>(a, p, s) : launch_queue<256, false>(a, p, s);
+  const fh_status st = a.mode == kModeWhole ? launch_queue_mode<kModeWhole>(a, p, s)
+                                            : launch_queue_mode<kModeWindowed>(a, p, s);
   if (st == FH_OK && p.ev_stop && hipEventRecord(p.ev_stop, s) != hipSuccess) return FH_EDEVICE;
   return st;
 }
@@ -758,6 +773,8 @@ fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStrea
 // ------------------------------------------------------------- batching --
 
 using namespace fh;
+
+constexpr int kBatchWholeThreads = 512;  // batches of whole-FFT maps (measured best of 256/512/1024)
 
 struct fh_batch_s {
   int32_t m = 0;
@@ -772,6 +789,7 @@ struct fh_batch_s {
   int32_t n_queue = 0, n_clears = 0;
   int32_t grid = 0;
   int32_t lds = 0;
+  int32_t threads = 256, mode = 0;  // persistent kernel: work-group size, compiled mode (0: per map)
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -798,6 +816,18 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
   int lds = 0;
   double total = 0;
   bool any_windowed = false;
+  // all whole-FFT maps: a kernel compiled for that mode alone, with 512-thread
+  // work-groups; otherwise both modes with 256 threads
+  bool all_whole = true;
+  for (int i = 0; i < m; ++i) {
+    if (!plans[i]) {
+      batch_free(b);
+      return FH_EINVAL;
+    }
+    all_whole &= reinterpret_cast<const fh_plan_s*>(plans[i])->p.tile.mode == kModeWhole;
+  }
+  b->threads = all_whole ? kBatchWholeThreads : 256;
+  b->mode = all_whole ? (int)kModeWhole : 0;
   for (int i = 0; i < m; ++i) {
     if (!plans[i] || !maps[i] || !peaks[i].row_ptr || peaks[i].n_peaks < 0 || peaks[i].n_peaks >= (1LL << 31) ||
         (peaks[i].n_peaks > 0 && !peaks[i].bin)) {
@@ -806,8 +836,8 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
     }
     const Plan& p = reinterpret_cast<const fh_plan_s*>(plans[i])->p;
     MapArgs a = p.args(peaks[i], maps[i]);
-    // one work-group size for the whole batch (256 threads), A staged in LDS
-    a.lds_bytes = lds_bytes_for_shape(a.n_f, a.rows, a.cols, 1, 256, &a.pitch);
+    // one work-group size for the whole batch, A staged in LDS
+    a.lds_bytes = lds_bytes_for_shape(a.n_f, a.rows, a.cols, 1, b->threads, &a.pitch);
     a.a_lds = 1;
     if (a.lds_bytes > kLdsBudget) {
       batch_free(b);
@@ -822,7 +852,7 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
     total += p.total_cost;
   }
   // units of all maps sized against the whole batch, longest first
-  const int resident = occupancy_grid(256, lds, 1 << 30);
+  const int resident = occupancy_grid(b->threads, lds, 1 << 30, b->mode);
   const double target = total / (4.0 * std::max(resident, 1));
   std::vector<Unit> units;
   std::vector<double> cost;
@@ -855,7 +885,8 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
     batch_free(b);
     return FH_EDEVICE;
   }
-  set_lds_attr<256, true>(lds);
+  if (b->mode == kModeWhole) set_lds_attr<kBatchWholeThreads, true, kModeWhole>(lds);
+  else set_lds_attr<256, true, 0>(lds);
   // capture: prologue (queue head, error words, split tiles cleared), rank
   // structures of windowed maps, one persistent kernel
   if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
@@ -871,8 +902,12 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
     if (any_windowed)
       hipLaunchKernelGGL(k_prepare_batch, dim3(2048), dim3(kPrepWaves * 64), kPrepLdsWords * 4, b->cap, b->d_maps,
                          m);
-    hipLaunchKernelGGL((k_queue<256, true>), dim3(b->grid), dim3(256), lds, b->cap, none, (const MapArgs*)b->d_maps,
-                       (const Unit*)b->d_queue, b->n_queue, b->d_head);
+    if (b->mode == kModeWhole)
+      hipLaunchKernelGGL((k_queue<kBatchWholeThreads, true, kModeWhole>), dim3(b->grid), dim3(kBatchWholeThreads), lds,
+                         b->cap, none, (const MapArgs*)b->d_maps, (const Unit*)b->d_queue, b->n_queue, b->d_head);
+    else
+      hipLaunchKernelGGL((k_queue<256, true, 0>), dim3(b->grid), dim3(256), lds, b->cap, none,
+                         (const MapArgs*)b->d_maps, (const Unit*)b->d_queue, b->n_queue, b->d_head);
     ok = hipStreamEndCapture(b->cap, &b->graph) == hipSuccess;
   }
   if (ok) ok = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;

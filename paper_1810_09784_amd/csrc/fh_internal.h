@@ -97,7 +97,7 @@ void split_units(const Plan& p, int32_t mi, double target, std::vector<Unit>& un
 
 // implemented in fh_hough.hip
 fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStream_t s);
-int occupancy_grid(int threads, int lds_bytes, int n_units);
+int occupancy_grid(int threads, int lds_bytes, int n_units, int mode);
 
 }  // namespace fh
 

@@ -76,7 +76,7 @@ static fh_tile_cfg auto_tile(const Plan& p) {
   c.tsplit = 64;
   if (p.n_x0 <= 6144 || p.n_J == 0) {
     c.mode = kModeWhole;
-    c.threads = 256;
+    c.threads = 512;
     c.cols = std::min(p.n_x0, 8192);
     int pitch = round_up(c.cols + 1, 4);
     int rows = (40 * 1024) / (pitch * 4);
@@ -393,7 +393,7 @@ extern "C" fh_status fh_plan(const fh_map_desc* d, const fh_tile_cfg* cfg, fh_pl
     int pitch;
     const int a_lds = lds_bytes_for_shape(n_f, c.rows, c.cols, 1, c.threads, nullptr) <= kLdsBudget;
     const int lds = lds_bytes_for_shape(n_f, c.rows, c.cols, a_lds, c.threads, &pitch);
-    const int resident = occupancy_grid(c.threads, lds, 1 << 30);
+    const int resident = occupancy_grid(c.threads, lds, 1 << 30, c.mode);
     split_units(p, 0, p.total_cost / (4.0 * std::max(resident, 1)), p.units, p.unit_cost, p.clears);
     // longest first
     std::vector<size_t> order(p.units.size());

@@ -49,7 +49,8 @@ def candidates(n_x0: int, n_k: int, n_fft: int) -> List[dict]:
                 tiles = ((n_k + rows - 1) // rows) * ts
                 if tiles < 128 or tiles > 65536:
                     continue
-                out.append(dict(mode=1, rows=rows, cols=n_x0, threads=256, tsplit=ts))
+                for th in (256, 512):
+                    out.append(dict(mode=1, rows=rows, cols=n_x0, threads=th, tsplit=ts))
     if n_x0 > 1024:
         for ntx in (1, 2, 3, 4, 6, 8, 12):
             cols = (n_x0 + ntx - 1) // ntx

@@ -98,6 +98,8 @@ TILES = [
     dict(mode=2, rows=1, cols=37, threads=256, tsplit=1),
     dict(mode=2, rows=2, cols=128, threads=512, tsplit=2),
     dict(mode=2, rows=5, cols=1000, threads=256, tsplit=1),
+    dict(mode=1, rows=8, cols=300, threads=1024, tsplit=2),
+    dict(mode=2, rows=1, cols=2000, threads=1024, tsplit=4),
 ]
 
 
