@@ -111,6 +111,12 @@ struct GMap {
 };
 
 // rank(i, j): number of peaks of FFT i with bin < j (0 <= j <= n_f).
+// T_i: the table entry, or for mid-FFT times the same binary64 expression the
+// plan evaluates, ((double)i + 0.5) * tfft, without the load.
+__device__ __forceinline__ double fft_time(const MapArgs& M, const GMap& G, int i) {
+  return M.t_uniform ? ((double)i + 0.5) * M.tfft : G.T[i];
+}
+
 __device__ __forceinline__ int peak_rank(const MapArgs& M, const GMap& G, int i, int j) {
   const unsigned long long e = G.rank[(size_t)(j >> 5) * M.n_fft + i];
   const unsigned below = (j & 31) ? ((1u << (j & 31)) - 1u) : 0u;
@@ -287,7 +293,7 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
       const int fi = f0 + min(lane, nb - 1);
       const int rp_l = min(max(G.row_ptr[f0 + min(lane, nb)], 0), M.n_peaks);
       const int rp_e = uniform(min(max(G.row_ptr[f0 + nb], 0), M.n_peaks));
-      const double Tf = G.T[fi];
+      const double Tf = fft_time(M, G, fi);
       int rb = nrows;
       if (mono) {
         int u = 0, w = nrows;  // first r with ib_r <= fi
@@ -333,7 +339,7 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
     }
   } else {
     // Per row: each lane owns one FFT, finds the peaks whose image can reach
-    // the tile's columns and walks them (four loads in flight per lane).
+    // the tile's columns and walks them eight at a time.
     for (int rl = 0; rl < nrows; ++rl) {
       const int ia = ia_s[rl], ib = ib_s[rl];
       const double C = G.C[r0 + rl];
@@ -342,7 +348,7 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
         const int i = qb + lane;
         const bool iv = i < ib;
         const int ic = iv ? i : ia;
-        const double T = G.T[ic];
+        const double T = fft_time(M, G, ic);
         const double s = C * T;
         // a superset of the bins whose image can meet [c0, c1): A_j >= c0 + s and
         // A_{j+1} < c1 + s, each widened by one column against rounding

@@ -1,0 +1,35 @@
+"""The package's search grids (host code that feeds fh_plan) against the
+oracle's transcription of Sec. VI."""
+import numpy as np
+import pytest
+
+from oracle import grids as OG
+from paper_1810_09784_amd import grids as G
+
+
+@pytest.mark.parametrize("n,tfft,band,ratio", [(3.0, 4.0, (200.0, 1200.0), 1e-2), (5.0, 2.0, (500.0, 600.0), 1e-3),
+                                               (2.0, 1.0, (100.0, 164.0), 0.5), (7.0, 8.0, (1936.0, 2000.0), 1e-4)])
+def test_k_grid_matches_the_oracle(n, tfft, band, ratio):
+    fd = 1.0 / tfft ** 2
+    ks, dks = G.k_grid(n, tfft, band[0], band[1], fd * ratio, fd)
+    ok, odk = OG.k_grid(n, tfft, band[0], band[1], fd * ratio, fd)
+    assert len(ks) == len(ok)
+    np.testing.assert_allclose(ks, ok, rtol=1e-11, atol=0)
+    np.testing.assert_allclose(dks, odk, rtol=1e-9, atol=0)
+    assert np.all(np.diff(ks) > 0)
+
+
+def test_n_grid_matches_the_oracle():
+    a = G.n_grid(4.0, 4.004, 2.0, 2000.0, 0.25, 1e5, samples=401)
+    b = OG.n_grid(4.0, 4.004, 2.0, 2000.0, 0.25, 1e5, samples=401)
+    assert len(a) == len(b)
+    np.testing.assert_allclose(a, b, rtol=1e-5)
+
+
+@pytest.mark.parametrize("n", [2.0, 3.0, 5.0, 7.0])
+def test_splice_matches_the_oracle(n):
+    a = G.splice(n, 800.0, 2.0, 4)
+    b = OG.splice(n, 800.0, 2.0, 4)
+    scale = max(lv.t_end for lv in a)
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(list(x), list(y), rtol=1e-12, atol=1e-12 * scale)

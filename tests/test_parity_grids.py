@@ -1,0 +1,77 @@
+"""Hough maps on the paper's own search layout (Sec. VI): the geometric k grid
+and T_FFT-spliced time/frequency rectangles, exact against the oracle, and
+the injected source found where the grids put it."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1810_09784_amd import grids, synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_09784_amd import fh
+    fh.lib()
+    return torch.device("cuda:0")
+
+
+def _run(dev, oracle, spec):
+    import torch
+    from paper_1810_09784_amd import fh
+    pm = S.make_peakmap(spec)
+    plan = fh.Plan.from_spec(spec)
+    H = fh.fh_hough(plan, torch.from_numpy(pm.row_ptr).to(dev), torch.from_numpy(pm.bin).to(dev))
+    got = H.cpu().numpy()
+    d = oracle.Desc.from_spec(spec)
+    ref = oracle.hough(d, pm.row_ptr, pm.bin)
+    assert np.array_equal(got, ref)
+    _, x0_min, dx0, _ = oracle.grid(d)
+    return got, x0_min, dx0
+
+
+def _band(f_lo, f_hi, tfft, margin):
+    lo = math.floor((f_lo - margin) * tfft) / tfft
+    hi = math.ceil((f_hi + margin) * tfft) / tfft
+    return lo, hi
+
+
+def test_geometric_k_grid_map(dev, oracle):
+    n, tfft, f_min, f_max = 5.0, 2.0, 500.0, 600.0
+    fd = 1.0 / tfft ** 2
+    ks, _ = grids.k_grid(n, tfft, f_min, f_max, fd * 1e-2, fd)
+    m = 700
+    f0 = 585.0
+    inj = S.Injection(f0=f0, tau=1.0 / (ks[m] * (n - 1) * f0 ** (n - 1)), n=n, amp=8.0)
+    spec = S.MapSpec("geo", n, tfft, f_min, f_max, 1800, ks, seed=11, injections=[inj])
+    H, x0_min, dx0 = _run(dev, oracle, spec)
+    r, c = np.unravel_index(int(np.argmax(H)), H.shape)
+    assert abs(r - m) <= 1
+    x0 = x0_min + (c + 0.5) * dx0
+    assert abs(x0 ** (1.0 / (1.0 - n)) - f0) < 1.0
+
+
+def test_spliced_levels_track_one_source(dev, oracle):
+    # the reference source of Sec. VI.D (f0, fdot0 = 1/T0^2): T_FFT = 2 s until its
+    # spindown falls by 4, then 4 s; each level's map finds it at the same k and at
+    # the frequency it has reached at the level's start
+    n, f0, t0 = 5.0, 590.0, 2.0
+    k = (1.0 / t0 ** 2) / f0 ** n
+    for lv in grids.splice(n, f0, t0, 2):
+        f_start = float(grids.power_law(lv.t_start, f0, k, n))
+        lo, hi = _band(lv.f_low, lv.f_high, lv.tfft, 8.0)
+        fd = 1.0 / lv.tfft ** 2
+        ks, _ = grids.k_grid(n, lv.tfft, lo, hi, fd * 1e-2, fd)
+        n_fft = int((lv.t_end - lv.t_start) / lv.tfft)
+        inj = S.Injection(f0=f_start, tau=1.0 / (k * (n - 1) * f_start ** (n - 1)), n=n, amp=6.0)
+        spec = S.MapSpec(f"level{lv.tfft}", n, lv.tfft, lo, hi, n_fft, ks, seed=12, injections=[inj])
+        H, x0_min, dx0 = _run(dev, oracle, spec)
+        r, c = np.unravel_index(int(np.argmax(H)), H.shape)
+        assert abs(r - int(np.argmin(np.abs(ks - k)))) <= 1
+        x0 = x0_min + (c + 0.5) * dx0
+        assert abs(x0 ** (1.0 / (1.0 - n)) - f_start) < 2.0 / lv.tfft
