@@ -98,3 +98,30 @@ def splice(n: float, f0: float, tfft0: float, levels: int):
         t_b = ((f0 / f_lo) ** (n - 1.0) - 1.0) / (k * (n - 1.0) * f0 ** (n - 1.0))
         out.append((t_l, t_a, t_b, f_lo, f_hi))
     return out
+
+
+def plan_bands(f_start: float, f_stop: float, width: float, tfft: float, enlarge: float, overlap: float):
+    """Analysed bands of Sec. IV stepping by width - overlap, each one's peakmap
+    band enlarged at the top by enlarge x its upper edge, edges on whole bins."""
+    df = 1.0 / tfft
+    bands = []
+    lo = f_start
+    while True:
+        hi = min(lo + width, f_stop)
+        a = math.floor(lo * tfft + 1e-9) / tfft
+        b = math.ceil(hi * tfft - 1e-9) / tfft
+        top = math.ceil(b * (1.0 + enlarge) * tfft - 1e-9) / tfft
+        bands.append((a, b, a, top))
+        if hi >= f_stop:
+            return bands
+        lo = hi - overlap
+
+
+def analysed_columns(n: float, f_hi: float, x0_min: float, dx0: float, n_x0: int):
+    """Brute force over every column: [first column whose centre's source
+    frequency is <= f_hi (compared in x: x0 >= f_hi^(1-n)), n_x0)."""
+    X = f_hi ** (1.0 - n)
+    for c in range(n_x0):
+        if x0_min + (c + 0.5) * dx0 >= X:
+            return c, n_x0
+    return n_x0, n_x0

@@ -101,3 +101,48 @@ def splice(n: float, f0: float, tfft0: float, levels: int) -> List[Level]:
         out.append(Level(tfft0 * 2 ** lev, tau * ((f0 / f_hi) ** (n - 1.0) - 1.0),
                          tau * ((f0 / f_lo) ** (n - 1.0) - 1.0), f_lo, f_hi))
     return out
+
+
+class Band(NamedTuple):
+    f_lo: float   # analysed band [f_lo, f_hi)
+    f_hi: float
+    pm_lo: float  # peakmap band: the analysed band enlarged at its high edge
+    pm_hi: float
+
+
+def plan_bands(f_start: float, f_stop: float, width: float, tfft: float, enlarge: float = 0.2,
+               overlap: float = 0.0) -> List[Band]:
+    """Interlaced analysed bands of Sec. IV covering [f_start, f_stop): each is
+    `width` Hz (the last one may be shorter), consecutive bands overlap by
+    `overlap` Hz, and each peakmap extends the band's top edge by `enlarge`
+    times that edge (rounded up to a whole bin), where the transformed noise
+    is densest.  Band edges are rounded to whole bins of 1/T_FFT."""
+    if not (0 < width and 0 <= overlap < width and f_start < f_stop and enlarge >= 0):
+        raise ValueError("bad band plan")
+    df = 1.0 / tfft
+    out = []
+    lo = f_start
+    while lo < f_stop - 1e-9:
+        hi = min(lo + width, f_stop)
+        a = math.floor(lo / df + 1e-9) * df
+        b = math.ceil(hi / df - 1e-9) * df
+        top = math.ceil(b * (1.0 + enlarge) / df - 1e-9) * df
+        out.append(Band(a, b, a, top))
+        if hi >= f_stop:
+            break
+        lo = hi - overlap
+    return out
+
+
+def analysed_columns(n: float, f_hi: float, x0_min: float, dx0: float, n_x0: int) -> Tuple[int, int]:
+    """Columns [col_lo, n_x0) of a map whose cell centre x0_min + (c + 0.5) dx0
+    lies at or above f_hi^(1-n), i.e. whose source frequency x0^(1/(1-n)) is at
+    most f_hi: the candidates of the extra (enlarged) band are left out."""
+    X = f_hi ** (1.0 - n)
+    c = int(math.ceil((X - x0_min) / dx0 - 0.5))
+    c = min(max(c, 0), n_x0)
+    while c > 0 and x0_min + (c - 1 + 0.5) * dx0 >= X:
+        c -= 1
+    while c < n_x0 and x0_min + (c + 0.5) * dx0 < X:
+        c += 1
+    return c, n_x0

@@ -33,3 +33,20 @@ def test_splice_matches_the_oracle(n):
     scale = max(lv.t_end for lv in a)
     for x, y in zip(a, b):
         np.testing.assert_allclose(list(x), list(y), rtol=1e-12, atol=1e-12 * scale)
+
+
+def test_band_plan_matches_the_oracle():
+    for args in ((100.0, 2000.0, 64.0, 2.0, 0.2, 8.0), (200.0, 300.0, 100.0, 4.0, 1.0 / 6.0, 0.0),
+                 (333.3, 999.9, 37.5, 8.0, 0.25, 5.0)):
+        a = G.plan_bands(*args)
+        b = OG.plan_bands(*args)
+        assert [tuple(x) for x in a] == [tuple(y) for y in b]
+
+
+@pytest.mark.parametrize("n,f_hi", [(2.0, 300.0), (3.0, 310.25), (5.0, 299.75), (7.0, 330.0)])
+def test_analysed_columns_match_the_oracle(n, f_hi):
+    pm_hi, pm_lo, tfft = 350.0, 200.0, 4.0
+    x0_min = pm_hi ** (1 - n)
+    dx0 = (n - 1) * (1 / tfft) * pm_hi ** (-n)
+    n_x0 = 5000
+    assert G.analysed_columns(n, f_hi, x0_min, dx0, n_x0) == OG.analysed_columns(n, f_hi, x0_min, dx0, n_x0)

@@ -84,3 +84,33 @@ def test_splice_levels_switch_where_the_spindown_falls_by_four(n):
             assert nxt[0] == 2 * tf and nxt[1] == pytest.approx(tb, rel=1e-12) and nxt[4] == pytest.approx(flo)
     # tau of Sec. VI.D: the spindown time scale f0 / (fdot0 (n - 1))
     assert lv[1][1] == pytest.approx(tau * (4.0 ** ((n - 1) / n) - 1.0), rel=1e-12)
+
+
+def test_band_plan_reproduces_the_papers_example_and_covers_the_range():
+    # Sec. IV: analysing [200, 300] Hz uses a peakmap of [200, 350] Hz (upper edge x 7/6)
+    (a, b, pa, pb), = G.plan_bands(200.0, 300.0, 100.0, 4.0, 1.0 / 6.0, 0.0)
+    assert (a, b, pa, pb) == (200.0, 300.0, 200.0, 350.0)
+    bands = G.plan_bands(100.0, 2000.0, 64.0, 2.0, 0.2, 8.0)
+    assert bands[0][0] == 100.0 and bands[-1][1] == 2000.0
+    for (a0, b0, _, _), (a1, b1, _, _) in zip(bands, bands[1:]):
+        assert a1 <= b0 and b0 - a1 == pytest.approx(8.0)   # interlaced: every frequency covered
+    for a, b, pa, pb in bands:
+        assert pa == a and pb >= 1.2 * b - 1e-9 and (pb - 1.2 * b) < 0.5
+
+
+@pytest.mark.parametrize("n", [2.0, 3.0, 5.0, 7.0])
+def test_analysed_columns_are_the_cells_of_the_analysed_band(n):
+    # the excluded columns are exactly those whose cell centre inverts (Eq. transform)
+    # to a source frequency above the analysed band's top
+    f_hi, pm_hi, tfft, pm_lo = 300.0, 350.0, 4.0, 200.0
+    df = 1.0 / tfft
+    x0_min = pm_hi ** (1 - n)
+    dx0 = (n - 1) * df * pm_hi ** (-n)
+    n_x0 = int(math.ceil(pm_hi * ((pm_hi / pm_lo) ** (n - 1) - 1) / ((n - 1) * df) - 1e-9))
+    lo, hi = G.analysed_columns(n, f_hi, x0_min, dx0, n_x0)
+    assert hi == n_x0 and 0 < lo < n_x0
+    f_centre = lambda c: (x0_min + (c + 0.5) * dx0) ** (1.0 / (1.0 - n))
+    assert f_centre(lo) <= f_hi * (1 + 1e-12) and f_centre(lo - 1) > f_hi * (1 - 1e-12)
+    # the same count from the inverse transform: columns between f_hi and pm_hi
+    approx = (f_hi ** (1 - n) - x0_min) / dx0
+    assert abs(lo - approx) <= 1.0

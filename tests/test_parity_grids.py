@@ -75,3 +75,34 @@ def test_spliced_levels_track_one_source(dev, oracle):
         assert abs(r - int(np.argmin(np.abs(ks - k)))) <= 1
         x0 = x0_min + (c + 0.5) * dx0
         assert abs(x0 ** (1.0 / (1.0 - n)) - f_start) < 2.0 / lv.tfft
+
+
+def test_enlarged_band_selection(dev, oracle):
+    # Sec. IV: to analyse [200, 300] Hz the peakmap covers [200, 350] Hz, and the
+    # candidates of the extra 50 Hz (the lowest x0 columns) are left out
+    import torch
+    from paper_1810_09784_amd import fh
+    from oracle import grids as OG, select as OS
+    band = grids.plan_bands(200.0, 300.0, 100.0, 4.0, 1.0 / 6.0, 0.0)[0]
+    assert (band.pm_lo, band.pm_hi) == (200.0, 350.0)
+    n, tfft = 3.0, 4.0
+    k = S.uniform_k(S.k_max_paper(tfft, band.pm_lo, n), 256)
+    f0 = 250.0  # source on the grid's k row 6
+    inj = S.Injection(f0=f0, tau=1.0 / (k[6] * (n - 1) * f0 ** (n - 1)), n=n, amp=5.0)
+    spec = S.MapSpec("enlarged", n, tfft, band.pm_lo, band.pm_hi, 2000, k, seed=13, injections=[inj])
+    pm = S.make_peakmap(spec)
+    plan = fh.Plan.from_spec(spec)
+    H = fh.fh_hough(plan, torch.from_numpy(pm.row_ptr).to(dev), torch.from_numpy(pm.bin).to(dev))
+    d = oracle.Desc.from_spec(spec)
+    ref_map = oracle.hough(d, pm.row_ptr, pm.bin)
+    assert np.array_equal(H.cpu().numpy(), ref_map)
+    _, x0_min, dx0, n_x0 = oracle.grid(d)
+    cols = grids.analysed_columns(n, band.f_hi, plan.info.x0_min, plan.info.dx0, plan.n_x0)
+    assert cols == OG.analysed_columns(n, band.f_hi, x0_min, dx0, n_x0)
+    got, _ = fh.fh_select(plan, H, 5, 5, 3, col_lo=cols[0], col_hi=cols[1])
+    ref = OS.select(ref_map, k, x0_min, dx0, n, 5, 5, 3, col_lo=cols[0], col_hi=cols[1])
+    assert [(c["row"], c["col"], c["count"], c["second"]) for c in got] == \
+           [(c["row"], c["col"], c["count"], c["second"]) for c in ref]
+    assert all(c["f0"] <= band.f_hi for c in got)
+    best = max(got, key=lambda c: c["cr"])
+    assert best["row"] == 6 and abs(best["f0"] - f0) < 0.5
