@@ -240,6 +240,37 @@ void fh_batch_destroy(fh_batch_t batch);
 fh_status fh_hough_batched(int32_t m, const fh_plan_t* plans, const fh_peaks* peaks, int32_t* const* maps,
                            void* stream);
 
+/* ------------------------------------------------------- coincidences --
+ * Sec. IV: candidates from two lists (two detectors, or two T_FFT portions of
+ * Sec. VI.D) are in coincidence when their distance in bins
+ *   d = sqrt(u*u + v*v),  u = (x0_b - x0_a') / dx,  v = (k_b - k_a) / dk
+ * is at most max_d (the paper uses 3), with dx = (dx0_a + dx0_b) / 2 and
+ * dk = (dk_a + dk_b) / 2 the mean bin sizes of the two candidates (dk is the
+ * local step of a non-uniform k grid).  x0_a' = x0_a + (nm1 * k_a) * dt moves
+ * a candidate of an earlier portion to the later portion's start along its
+ * line x = x0 + (n-1) k t (Sec. IV, Eq. transform): nm1 = n - 1 and dt are
+ * per segment; with dt = 0 (or NULL arrays) x0_a' = x0_a.  Every operation
+ * is one binary64 operation in this order, no contraction.
+ * Lists are grouped by segment (a map, or a braking index for portions):
+ * a_off / b_off (DEVICE int32 [n_seg + 1], non-decreasing) delimit each
+ * segment's points, and only points of the same segment are compared. */
+typedef struct {
+  double x0, k;     /* candidate cell */
+  double dx0, dk;   /* bin sizes of its map at that cell */
+} fh_point;
+
+/* Pairs (DEVICE int32 [cap][2], indices into a and b) of all coincident
+ * points, in no particular order, their distances (DEVICE double [cap], may
+ * be NULL) and the total number of pairs (*count, DEVICE int32, set by the
+ * call; pairs beyond cap are counted but not written).  a holds na points and
+ * a_off[n_seg] = na, b holds nb points and b_off[n_seg] = nb (offsets outside
+ * [0, na] / [0, nb] are clipped).  nm1, dt: DEVICE double [n_seg] or NULL.
+ * Asynchronous on `stream`; allocates nothing.  Errors: FH_EINVAL (negative
+ * sizes, NULL arrays that are needed, max_d not finite or < 0). */
+fh_status fh_coincide(int32_t n_seg, int32_t na, const int32_t* a_off, const fh_point* a, int32_t nb,
+                      const int32_t* b_off, const fh_point* b, const double* nm1, const double* dt, double max_d,
+                      int32_t* pairs, double* dist, int32_t cap, int32_t* count, void* stream);
+
 const char* fh_status_str(fh_status s);
 /* Library version string, and the gfx architecture it was built for. */
 const char* fh_version(void);

@@ -94,6 +94,9 @@ SIGNATURES = {
     "fh_tiles": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
     "fh_propose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "fh_coincide": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                              C.c_void_p]),
     "fh_status_str": (C.c_char_p, [C.c_int]),
     "fh_version": (C.c_char_p, []),
 }
@@ -256,6 +259,45 @@ def fh_select(plan: Plan, hmap, sq_k: int, sq_x0: int, min_dk: int = 3, cr_thr: 
         import numpy as np
         return np.ctypeslib.as_array(buf)[:m].copy(), int(n.value)
     return [buf[i].as_dict() for i in range(m)], int(n.value)
+
+
+def fh_coincide(a_off, a, b_off, b, max_d: float = 3.0, nm1=None, dt=None, cap: Optional[int] = None,
+                stream=None):
+    """Coincident pairs of two candidate lists (Sec. IV).  a, b: float64 CUDA
+    tensors [n, 4] of (x0, k, dx0, dk); a_off, b_off: int32 CUDA tensors
+    [n_seg + 1] delimiting each segment; nm1, dt: float64 CUDA tensors [n_seg]
+    (move a's candidates along their lines by dt) or None.  Returns
+    (pairs int32 [m, 2], dist float64 [m], total) with m = min(total, cap)."""
+    import torch
+    n_seg = int(a_off.numel()) - 1
+    if n_seg < 0 or int(b_off.numel()) != n_seg + 1:
+        raise ValueError("a_off and b_off need n_seg + 1 entries")
+    for t, dt_ in ((a, torch.float64), (b, torch.float64), (a_off, torch.int32), (b_off, torch.int32)):
+        assert t.is_cuda and t.dtype == dt_ and t.is_contiguous()
+    if a.dim() != 2 or a.shape[1] != 4 or b.dim() != 2 or b.shape[1] != 4:
+        raise ValueError("points are [n, 4] float64: x0, k, dx0, dk")
+    na, nb = int(a.shape[0]), int(b.shape[0])
+    dev = a.device
+    count = torch.empty(1, dtype=torch.int32, device=dev)
+    opt = lambda t: C.c_void_p(_ptr(t)) if t is not None else None
+
+    def run(c):
+        pairs = torch.empty((max(c, 1), 2), dtype=torch.int32, device=dev)
+        dist = torch.empty(max(c, 1), dtype=torch.float64, device=dev)
+        _check(lib().fh_coincide(n_seg, na, opt(a_off), opt(a) if na else None, nb, opt(b_off),
+                                 opt(b) if nb else None, opt(nm1), opt(dt), float(max_d), C.c_void_p(_ptr(pairs)),
+                                 C.c_void_p(_ptr(dist)), int(c), C.c_void_p(_ptr(count)), _stream(stream)),
+               "fh_coincide")
+        return pairs, dist, int(count.item())
+
+    if cap is not None:
+        pairs, dist, total = run(int(cap))
+        m = min(total, int(cap))
+        return pairs[:m], dist[:m], total
+    pairs, dist, total = run(4 * max(na, nb, 1))
+    if total > 4 * max(na, nb, 1):  # every pair wanted: run again with room for all
+        pairs, dist, total = run(total)
+    return pairs[:total], dist[:total], total
 
 
 class Batch:

@@ -1,0 +1,119 @@
+"""fh_coincide (GPU) against the oracle's brute force, and coincidences of
+two detectors' candidates from real Hough maps."""
+import numpy as np
+import pytest
+
+from oracle import coinc as OC
+from paper_1810_09784_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_09784_amd import fh
+    fh.lib()
+    return torch.device("cuda:0")
+
+
+def _lists(rng, sizes_a, sizes_b):
+    # one centre and bin size per segment, shared by both lists, so that pairs exist
+    n_seg = len(sizes_a)
+    centre = rng.normal(size=(n_seg, 2)) * 10
+    bins = rng.uniform(0.05, 0.2, size=(n_seg, 2))
+
+    def pts(sizes):
+        out = []
+        for s, m in enumerate(sizes):
+            for _ in range(m):
+                x0, k = centre[s] + rng.normal(size=2) * bins[s] * 3
+                out.append((x0, k, bins[s, 0] * rng.uniform(0.9, 1.1), bins[s, 1] * rng.uniform(0.9, 1.1)))
+        return np.array(out, dtype=np.float64).reshape(-1, 4)
+    off = lambda sizes: np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    return off(sizes_a), pts(sizes_a), off(sizes_b), pts(sizes_b)
+
+
+def _gpu(dev, a_off, a, b_off, b, **kw):
+    import torch
+    from paper_1810_09784_amd import fh
+    T = lambda x, dt: torch.as_tensor(x, dtype=dt).to(dev).contiguous()
+    extra = {k: (T(v, torch.float64) if v is not None else None) for k, v in kw.items() if k in ("nm1", "dt")}
+    return fh.fh_coincide(T(a_off, torch.int32), T(a, torch.float64), T(b_off, torch.int32), T(b, torch.float64),
+                          max_d=kw.get("max_d", 3.0), cap=kw.get("cap"), **extra)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_segments_match_oracle(dev, seed):
+    rng = np.random.default_rng(50 + seed)
+    n_seg = int(rng.integers(1, 30))
+    sa = rng.integers(0, 60, n_seg)
+    sb = rng.integers(0, 60, n_seg)
+    sa[rng.integers(0, n_seg)] = 0  # an empty segment
+    a_off, a, b_off, b = _lists(rng, sa, sb)
+    nm1 = dt = None
+    if seed % 2:
+        nm1 = rng.uniform(1, 6, n_seg)
+        dt = rng.uniform(-1e-3, 1e-3, n_seg)
+    pairs, dist, total = _gpu(dev, a_off, a, b_off, b, nm1=nm1, dt=dt)
+    ref = OC.coincide(a_off, a, b_off, b, 3.0, nm1=nm1, dt=dt)
+    got = {(int(i), int(j)): float(d) for (i, j), d in zip(pairs.cpu().numpy(), dist.cpu().numpy())}
+    assert len(ref) > 100 and total == len(ref) and got == ref
+
+
+def test_cap_counts_all_but_writes_cap(dev):
+    rng = np.random.default_rng(7)
+    a_off, a, b_off, b = _lists(rng, [50], [50])
+    ref = OC.coincide(a_off, a, b_off, b, 3.0)
+    assert len(ref) > 10
+    pairs, dist, total = _gpu(dev, a_off, a, b_off, b, cap=10)
+    assert total == len(ref) and pairs.shape[0] == 10
+    for (i, j), d in zip(pairs.cpu().numpy(), dist.cpu().numpy()):
+        assert ref[(int(i), int(j))] == d
+
+
+def test_bad_arguments(dev):
+    import torch
+    from paper_1810_09784_amd import fh
+    z = torch.zeros((1, 4), dtype=torch.float64, device=dev)
+    off = torch.tensor([0, 1], dtype=torch.int32, device=dev)
+    with pytest.raises(fh.FHError):
+        fh.fh_coincide(off, z, off, z, max_d=float("nan"))
+    with pytest.raises(fh.FHError):
+        fh.fh_coincide(off, z, off, z, max_d=-1.0)
+
+
+def test_two_detectors_see_the_injection(dev, oracle):
+    # the same power-law source in two detectors' noise: fh_hough + fh_select on
+    # each, then the candidate lists are joined; the injection's candidates coincide
+    import torch
+    from paper_1810_09784_amd import fh
+    from oracle import select as OS
+    base = S.cfg_single_small()
+    pts, refs, best = [], [], []
+    for seed in (21, 22):
+        spec = S.MapSpec(f"det{seed}", base.n, base.tfft, base.f_min, base.f_max, base.n_fft, base.k, seed=seed,
+                         injections=[S.Injection(f0=575.0, tau=1.2e4, n=base.n, amp=3.0)])
+        pm = S.make_peakmap(spec)
+        plan = fh.Plan.from_spec(spec)
+        H = fh.fh_hough(plan, torch.from_numpy(pm.row_ptr).to(dev), torch.from_numpy(pm.bin).to(dev))
+        got, _ = fh.fh_select(plan, H, 4, 6, 3)
+        d = oracle.Desc.from_spec(spec)
+        ref_map = oracle.hough(d, pm.row_ptr, pm.bin)
+        _, x0_min, dx0, _ = oracle.grid(d)
+        ref = OS.select(ref_map, spec.k, x0_min, dx0, spec.n, 4, 6, 3)
+        assert [(c["row"], c["col"]) for c in got] == [(c["row"], c["col"]) for c in ref]
+        dk = spec.k[1] - spec.k[0]
+        pts.append(np.array([[c["x0"], c["k"], dx0, dk] for c in got], dtype=np.float64))
+        refs.append([(c["x0"], c["k"], dx0, dk) for c in ref])
+        best.append(int(np.argmax([c["cr"] for c in ref])))
+    a_off = np.array([0, len(pts[0])], np.int32)
+    b_off = np.array([0, len(pts[1])], np.int32)
+    pairs, dist, total = _gpu(dev, a_off, pts[0], b_off, pts[1])
+    ref = OC.coincide(a_off, refs[0], b_off, refs[1], 3.0)
+    got = {(int(i), int(j)): float(d) for (i, j), d in zip(pairs.cpu().numpy(), dist.cpu().numpy())}
+    assert got == ref
+    # each detector's strongest candidate is the injection, and the two coincide
+    assert (best[0], best[1]) in got
