@@ -117,3 +117,45 @@ def test_two_detectors_see_the_injection(dev, oracle):
     assert got == ref
     # each detector's strongest candidate is the injection, and the two coincide
     assert (best[0], best[1]) in got
+
+
+def test_chaining_spliced_portions(dev, oracle):
+    # Sec. VI.D: candidates of the T_FFT = 2 s portion, moved along their lines to the
+    # start of the 4 s portion, coincide with that portion's candidates for the same source
+    import math
+    import torch
+    from paper_1810_09784_amd import fh, grids
+    from oracle import select as OS
+    n, f0, t0 = 5.0, 590.0, 2.0
+    k = (1.0 / t0 ** 2) / f0 ** n
+    lists, refs, best, starts = [], [], [], []
+    for lv in grids.splice(n, f0, t0, 2):
+        f_start = float(grids.power_law(lv.t_start, f0, k, n))
+        lo = math.floor((lv.f_low - 8.0) * lv.tfft) / lv.tfft
+        hi = math.ceil((lv.f_high + 8.0) * lv.tfft) / lv.tfft
+        fd = 1.0 / lv.tfft ** 2
+        ks, dks = grids.k_grid(n, lv.tfft, lo, hi, fd * 1e-2, fd)
+        inj = S.Injection(f0=f_start, tau=1.0 / (k * (n - 1) * f_start ** (n - 1)), n=n, amp=6.0)
+        spec = S.MapSpec(f"lv{lv.tfft}", n, lv.tfft, lo, hi, int((lv.t_end - lv.t_start) / lv.tfft), ks, seed=31,
+                         injections=[inj])
+        pm = S.make_peakmap(spec)
+        plan = fh.Plan.from_spec(spec)
+        H = fh.fh_hough(plan, torch.from_numpy(pm.row_ptr).to(dev), torch.from_numpy(pm.bin).to(dev))
+        got, _ = fh.fh_select(plan, H, 5, 5, 3)
+        d = oracle.Desc.from_spec(spec)
+        ref_map = oracle.hough(d, pm.row_ptr, pm.bin)
+        _, x0_min, dx0, _ = oracle.grid(d)
+        ref = OS.select(ref_map, ks, x0_min, dx0, n, 5, 5, 3)
+        assert [(c["row"], c["col"]) for c in got] == [(c["row"], c["col"]) for c in ref]
+        lists.append(np.array([[c["x0"], c["k"], dx0, dks[c["row"]]] for c in got], dtype=np.float64))
+        refs.append([(c["x0"], c["k"], dx0, dks[c["row"]]) for c in ref])
+        best.append(int(np.argmax([c["cr"] for c in ref])))
+        starts.append(lv.t_start)
+    a_off = np.array([0, len(lists[0])], np.int32)
+    b_off = np.array([0, len(lists[1])], np.int32)
+    nm1, dt = np.array([n - 1.0]), np.array([starts[1] - starts[0]])
+    pairs, dist, total = _gpu(dev, a_off, lists[0], b_off, lists[1], nm1=nm1, dt=dt)
+    ref = OC.coincide(a_off, refs[0], b_off, refs[1], 3.0, nm1=nm1, dt=dt)
+    got = {(int(i), int(j)): float(d) for (i, j), d in zip(pairs.cpu().numpy(), dist.cpu().numpy())}
+    assert got == ref
+    assert (best[0], best[1]) in got
