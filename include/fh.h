@@ -271,6 +271,31 @@ fh_status fh_coincide(int32_t n_seg, int32_t na, const int32_t* a_off, const fh_
                       const int32_t* b_off, const fh_point* b, const double* nm1, const double* dt, double max_d,
                       int32_t* pairs, double* dist, int32_t cap, int32_t* count, void* stream);
 
+/* --------------------------------------------------------- follow-up --
+ * The synthetic part of the follow-up of Sec. V: with a candidate's source
+ * parameters (f0, k) every peak (i, j) of the peakmap is moved by the drift
+ * of the power law of Eq. powlaws, j -> j - (b_i - b_0) with
+ *   b_i = floor((f(T_i) - f_min) * tfft),  b_0 = floor((f0 - f_min) * tfft),
+ *   f(T) = f0 / (1 + ((k * (n-1)) * pow(f0, n-1)) * T)^(1/(n-1))  (pow),
+ * so that the source's peaks gather in bin b_0; the moved peaks are then
+ * projected on the frequency axis and the count y in bin b_0 gets the
+ * critical ratio CR = (y - mu) / sigma against the bins b_0 - w .. b_0 + w
+ * outside b_0 - guard .. b_0 + guard (population statistics from exact sums,
+ * binary64: mu = S/N, var = S2/N - mu^2, sigma = sqrt(var); sigma = 0 gives
+ * CR = NaN).  Peaks with a bin outside [0, n_f) are skipped.  The plan gives
+ * n, tfft, f_min and the times T_i. */
+typedef struct {
+  int32_t y, pad;            /* peaks in bin b_0 after the move */
+  double mu, sigma, cr;
+} fh_projection;
+
+/* n_cand candidates, f0 and k DEVICE double [n_cand]; hist DEVICE int32
+ * [n_cand][2w+1] (bin b_0 + d at index w + d) written; out HOST [n_cand].
+ * 1 <= w <= 4096, 0 <= guard < w.  Synchronises `stream`.  Errors:
+ * FH_EINVAL, FH_EDEVICE. */
+fh_status fh_project(fh_plan_t plan, const fh_peaks* peaks, int32_t n_cand, const double* f0, const double* k,
+                     int32_t w, int32_t guard, int32_t* hist, fh_projection* out, void* stream);
+
 const char* fh_status_str(fh_status s);
 /* Library version string, and the gfx architecture it was built for. */
 const char* fh_version(void);

@@ -11,7 +11,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfh.so")
-SOURCES = ["fh_plan.cpp", "fh_hough.hip", "fh_select.hip", "fh_cnn.hip", "fh_coinc.hip"]
+SOURCES = ["fh_plan.cpp", "fh_hough.hip", "fh_select.hip", "fh_cnn.hip", "fh_coinc.hip", "fh_follow.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

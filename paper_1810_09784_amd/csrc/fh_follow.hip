@@ -1,0 +1,101 @@
+// Follow-up projection (Sec. V on peakmaps): peaks moved by a candidate's
+// power-law drift, histogrammed around the candidate's initial bin, and the
+// critical ratio of that bin.  One work-group per candidate; threads take
+// FFTs, evaluate the drift once per FFT and add the FFT's moved peaks into
+// an LDS histogram.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fh_internal.h"
+
+namespace fh {
+
+template <typename T>
+using gfo = __attribute__((address_space(1))) T*;
+
+constexpr int kProjThreads = 256;
+constexpr int kProjMaxW = 4096;
+
+__global__ void __launch_bounds__(kProjThreads)
+    k_project(const int32_t* row_ptr_, const int32_t* bin_, int n_peaks, int n_fft, int n_f, const double* T_,
+              double n, double tfft, double f_min, const double* f0_, const double* k_, int w, int32_t* hist_) {
+  extern __shared__ int hs[];
+  const gfo<const int32_t> row_ptr = (gfo<const int32_t>)row_ptr_;
+  const gfo<const int32_t> bin = (gfo<const int32_t>)bin_;
+  const gfo<const double> T = (gfo<const double>)T_;
+  const int c = blockIdx.x;
+  const int nb = 2 * w + 1;
+  for (int x = threadIdx.x; x < nb; x += blockDim.x) hs[x] = 0;
+  __syncthreads();
+  const double f0 = ((gfo<const double>)f0_)[c];
+  const double k = ((gfo<const double>)k_)[c];
+  const double nm1 = n - 1.0;
+  const double a = (k * nm1) * pow(f0, nm1);
+  const double e = 1.0 / nm1;
+  const double b0 = floor((f0 - f_min) * tfft);
+  for (int i = threadIdx.x; i < n_fft; i += blockDim.x) {
+    const double f = f0 / pow(1.0 + a * T[i], e);
+    const double bi = floor((f - f_min) * tfft);
+    // the drift in bins; |bi - b0| is below n_f + 1 whenever it matters
+    const double sh = bi - b0;
+    if (!(fabs(sh) < 2147483647.0)) continue;
+    const int shift = (int)sh;
+    const int lo = min(max(row_ptr[i], 0), n_peaks);
+    const int hi = min(max(row_ptr[i + 1], lo), n_peaks);
+    for (int p = lo; p < hi; ++p) {
+      const int j = bin[p];
+      if ((unsigned)j >= (unsigned)n_f) continue;
+      const long long d = (long long)j - shift - (long long)b0;  // moved bin relative to b0
+      if (d >= -w && d <= w) atomicAdd(&hs[(int)d + w], 1);
+    }
+  }
+  __syncthreads();
+  gfo<int32_t> out = (gfo<int32_t>)hist_ + (size_t)c * nb;
+  for (int x = threadIdx.x; x < nb; x += blockDim.x) out[x] = hs[x];
+}
+
+}  // namespace fh
+
+using namespace fh;
+
+extern "C" fh_status fh_project(fh_plan_t h, const fh_peaks* peaks, int32_t n_cand, const double* f0, const double* k,
+                                int32_t w, int32_t guard, int32_t* hist, fh_projection* out, void* stream) {
+  if (!h || !peaks || n_cand < 0 || w < 1 || w > kProjMaxW || guard < 0 || guard >= w) return FH_EINVAL;
+  if (n_cand > 0 && (!f0 || !k || !hist || !out)) return FH_EINVAL;
+  const Plan& p = reinterpret_cast<const Plan&>(*h);
+  if (!peaks->row_ptr || peaks->n_peaks < 0 || peaks->n_peaks >= (1LL << 31) || (peaks->n_peaks > 0 && !peaks->bin))
+    return FH_EINVAL;
+  if (n_cand == 0) return FH_OK;
+  hipStream_t s = (hipStream_t)stream;
+  const int nb = 2 * w + 1;
+  hipLaunchKernelGGL(k_project, dim3((unsigned)n_cand), dim3(kProjThreads), nb * sizeof(int), s, peaks->row_ptr,
+                     peaks->bin, (int)peaks->n_peaks, p.desc.n_fft, p.n_f, p.dT, p.desc.n, p.desc.tfft, p.desc.f_min,
+                     f0, k, (int)w, hist);
+  if (hipGetLastError() != hipSuccess) return FH_EDEVICE;
+  std::vector<int32_t> hh((size_t)n_cand * nb);
+  if (hipMemcpyAsync(hh.data(), hist, hh.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FH_EDEVICE;
+  for (int c = 0; c < n_cand; ++c) {
+    const int32_t* y = &hh[(size_t)c * nb];
+    long long S = 0, S2 = 0, N = 0;
+    for (int x = 0; x < nb; ++x) {
+      if (x >= w - guard && x <= w + guard) continue;
+      S += y[x];
+      S2 += (long long)y[x] * y[x];
+      ++N;
+    }
+    fh_projection& o = out[c];
+    std::memset(&o, 0, sizeof(o));
+    o.y = y[w];
+    o.mu = (double)S / (double)N;
+    const double ex2 = (double)S2 / (double)N;
+    const double var = ex2 - o.mu * o.mu;
+    o.sigma = std::sqrt(var);
+    o.cr = o.sigma > 0.0 ? ((double)o.y - o.mu) / o.sigma : std::nan("");
+  }
+  return FH_OK;
+}

@@ -57,6 +57,10 @@ class Candidate(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_ if f != "pad"}
 
 
+class Projection(C.Structure):
+    _fields_ = [("y", C.c_int32), ("pad", C.c_int32), ("mu", C.c_double), ("sigma", C.c_double), ("cr", C.c_double)]
+
+
 class PlanInfo(C.Structure):
     _fields_ = [("n_f", C.c_int32), ("n_x0", C.c_int32), ("n_k", C.c_int32), ("n_fft", C.c_int32),
                 ("x0_min", C.c_double), ("dx0", C.c_double), ("tile", TileCfg), ("n_tiles", C.c_int64),
@@ -97,6 +101,8 @@ SIGNATURES = {
     "fh_coincide": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_double, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                               C.c_void_p]),
+    "fh_project": (C.c_int, [C.c_void_p, C.POINTER(Peaks), C.c_int32, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                             C.c_void_p, C.c_void_p, C.c_void_p]),
     "fh_status_str": (C.c_char_p, [C.c_int]),
     "fh_version": (C.c_char_p, []),
 }
@@ -259,6 +265,23 @@ def fh_select(plan: Plan, hmap, sq_k: int, sq_x0: int, min_dk: int = 3, cr_thr: 
         import numpy as np
         return np.ctypeslib.as_array(buf)[:m].copy(), int(n.value)
     return [buf[i].as_dict() for i in range(m)], int(n.value)
+
+
+def fh_project(plan: Plan, row_ptr, bin_, f0, k, w: int = 40, guard: int = 2, stream=None):
+    """Follow-up projection of the peakmap for each candidate (f0, k): float64
+    CUDA tensors [n_cand].  Returns (hist int32 CUDA [n_cand, 2w+1], list of
+    dicts y, mu, sigma, cr)."""
+    import torch
+    n = int(f0.numel())
+    assert f0.is_cuda and k.is_cuda and f0.dtype == torch.float64 and k.dtype == torch.float64 and k.numel() == n
+    assert f0.is_contiguous() and k.is_contiguous()
+    hist = torch.empty((max(n, 1), 2 * int(w) + 1), dtype=torch.int32, device=f0.device)
+    out = (Projection * max(n, 1))()
+    pk = peaks_struct(row_ptr, bin_)
+    _check(lib().fh_project(plan.handle, C.byref(pk), n, C.c_void_p(_ptr(f0)), C.c_void_p(_ptr(k)), int(w),
+                            int(guard), C.c_void_p(_ptr(hist)), out,
+                            _stream(stream)), "fh_project")
+    return hist[:n], [{"y": out[i].y, "mu": out[i].mu, "sigma": out[i].sigma, "cr": out[i].cr} for i in range(n)]
 
 
 def fh_coincide(a_off, a, b_off, b, max_d: float = 3.0, nm1=None, dt=None, cap: Optional[int] = None,

@@ -1,0 +1,83 @@
+"""Follow-up on peakmaps (Sec. V): fh_project and the over-resolved maps
+around candidates, against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import followup as OF
+from paper_1810_09784_amd import synth as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_09784_amd import fh
+    fh.lib()
+    return torch.device("cuda:0")
+
+
+def _same(a, b):
+    return a == b or (math.isnan(a) and math.isnan(b))
+
+
+def test_projection_matches_oracle_and_lifts_the_source(dev, oracle):
+    import torch
+    from paper_1810_09784_amd import fh
+    spec = S.cfg_single_small()
+    inj = spec.injections[0]
+    pm = S.make_peakmap(spec)
+    plan = fh.Plan.from_spec(spec)
+    rp, bn = torch.from_numpy(pm.row_ptr).to(dev), torch.from_numpy(pm.bin).to(dev)
+    H = fh.fh_hough(plan, rp, bn)
+    cands, _ = fh.fh_select(plan, H, 5, 5, 3)
+    rng = np.random.default_rng(4)
+    f0s = [c["f0"] for c in cands] + [inj.f0] + list(rng.uniform(505, 595, 8))
+    ks = [c["k"] for c in cands] + [inj.k] + list(rng.uniform(0, 2 * inj.k, 8))
+    f0t = torch.tensor(f0s, dtype=torch.float64, device=dev)
+    kt = torch.tensor(ks, dtype=torch.float64, device=dev)
+    for w, guard in ((40, 2), (5, 0)):
+        hist, res = fh.fh_project(plan, rp, bn, f0t, kt, w=w, guard=guard)
+        hist = hist.cpu().numpy()
+        for i, (f0, k) in enumerate(zip(f0s, ks)):
+            h_ref, r_ref = OF.project(pm.row_ptr, pm.bin, spec.times(), spec.n, spec.tfft, spec.f_min, spec.n_f,
+                                      f0, k, w, guard)
+            assert list(hist[i]) == h_ref
+            for key in ("y", "mu", "sigma", "cr"):
+                assert _same(res[i][key], r_ref[key]), (i, key, res[i][key], r_ref[key])
+    # the injection (true parameters) stands out in its projection; random ones do not
+    _, res = fh.fh_project(plan, rp, bn, f0t, kt, w=40, guard=2)
+    assert res[len(cands)]["cr"] > 20
+    assert max(r["cr"] for r in res[len(cands) + 1:]) < 8
+
+
+def test_over_resolved_maps_match_oracle_and_refine(dev, oracle):
+    import torch
+    from paper_1810_09784_amd import fh, followup
+    spec = S.cfg_single_small(noiseless=True)
+    inj = spec.injections[0]
+    pm = S.make_peakmap(spec)
+    plan = fh.Plan.from_spec(spec)
+    rp, bn = torch.from_numpy(pm.row_ptr).to(dev), torch.from_numpy(pm.bin).to(dev)
+    H = fh.fh_hough(plan, rp, bn)
+    r, c = np.unravel_index(int(torch.argmax(H).item()), tuple(H.shape))
+    dx0, dk = plan.info.dx0, float(spec.k[1] - spec.k[0])
+    coarse = {"x0": plan.info.x0_min + (c + 0.5) * dx0, "k": float(spec.k[r])}
+    extra = {"x0": coarse["x0"] + 2.0 * dx0, "k": coarse["k"] + 1.0 * dk}  # a neighbour cell too
+    out = followup.refine(dev, spec, rp, bn, [coarse, extra], dx0, dk, over=10, half=3)
+    for cand, (m, g, x0r, kr, cnt) in zip([coarse, extra], out):
+        x0_min, dxf, n_x0, ks = OF.roi_grid(cand["x0"], cand["k"], dx0, dk, 10, 3)
+        assert (x0_min, dxf, n_x0) == (g.x0_min, g.dx0, g.n_x0) and list(ks) == list(g.k)
+        d = oracle.Desc(spec.n, spec.tfft, spec.f_min, spec.f_max, spec.n_fft, ks, x0_min=x0_min, dx0=dxf,
+                        n_x0=n_x0)
+        assert np.array_equal(m.cpu().numpy(), oracle.hough(d, pm.row_ptr, pm.bin))
+    # the refined cell of the best candidate is nearer the true source than the coarse cell
+    x0_true = inj.f0 ** (1.0 - spec.n)
+    _, _, x0r, kr, cnt = out[0]
+    assert abs(x0r - x0_true) < abs(coarse["x0"] - x0_true) or abs(x0r - x0_true) <= 0.1 * dx0
+    assert abs(kr - inj.k) <= 0.1 * dk + 1e-30
+    assert cnt >= int(H.max().item())
