@@ -1,0 +1,224 @@
+"""The full sweep: a search layout of many generalized FrequencyHough maps.
+
+Every braking index n in {2, 2.5, ..., 7} x T_FFT in {2, 4, 8} s over 30
+sub-bands of 64 Hz from 100 Hz (up to 2020 Hz), T_obs = 5 days.  A peakmap
+per (band, T_FFT) is shared by the 11 braking indices (90 peakmaps, 990 maps);
+each map has 256 uniform k rows on [0, k_max], k_max = (1/T_FFT^2)/f_min^n
+(Sec. VI.B), and the x0 grid of Sec. VI.C.  Injections: 200 power-law
+sources, each drawn into one (band, T_FFT) peakmap with its n from the grid,
+f0 inside the band, k on one of the rows 2 .. n_k/2 - 1 of its map, and added
+power a uniform in [amp_lo, amp_hi].
+
+One run: all maps in one batched persistent launch (captured graph), the
+plain selection (sq_k x sq_x0 squares, second candidate 3 rows away) on
+every map, the tile CNN's scores of every 64 x 64 tile and its top tiles,
+and the detection efficiency of the plain selection and of the selection
+restricted to the proposed tiles (a detection: a candidate with CR >= thr
+within 3 bins of the injection's true cell in its own map).  Candidates
+farther than 10 bins from every injection of their map count as noise.
+"""
+from __future__ import annotations
+
+import math
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import synth as S
+
+N_VALUES = tuple(2.0 + 0.5 * i for i in range(11))
+TFFTS = (2.0, 4.0, 8.0)
+T_OBS = 5 * 86400.0
+N_K = 256
+
+
+def band_edges(n_bands: int = 30, f_start: float = 100.0, width: float = 64.0):
+    return [(f_start + width * b, f_start + width * (b + 1)) for b in range(n_bands)]
+
+
+class Sweep:
+    """Inputs, plans and maps of the sweep, resident on the GPU."""
+
+    def __init__(self, dev, seed: int = 5, n_values=N_VALUES, tffts=TFFTS, n_bands: int = 30, t_obs: float = T_OBS,
+                 n_k: int = N_K, n_inj: int = 200, amp_lo: float = 1.0, amp_hi: float = 4.0, log=None):
+        import torch
+        from . import fh
+        self.dev = dev
+        rng = np.random.default_rng(seed)
+        self.bands = band_edges(n_bands)
+        self.n_values, self.tffts = tuple(n_values), tuple(tffts)
+        # injections: (band, tfft index, n index, f0, k, amp)
+        inj = []
+        for _ in range(n_inj):
+            b = int(rng.integers(len(self.bands)))
+            ti = int(rng.integers(len(self.tffts)))
+            ni = int(rng.integers(len(self.n_values)))
+            lo, hi = self.bands[b]
+            n = self.n_values[ni]
+            k_max = (1.0 / self.tffts[ti] ** 2) / lo ** n
+            # on a k row of its map: a uniform grid this coarse moves a track by many
+            # columns per row over days, so off-row sources smear over the map
+            k = float(S.uniform_k(k_max, n_k)[int(rng.integers(2, n_k // 2))])
+            f0 = float(rng.uniform(lo + 4.0, hi - 4.0))
+            inj.append((b, ti, ni, f0, k, float(rng.uniform(amp_lo, amp_hi))))
+        self.injections = inj
+        self.peakmaps = {}   # (band, ti) -> (row_ptr, bin)
+        self.maps = []       # dicts: band, ti, ni, plan, hmap, peaks key, U
+        self.U = 0
+        t = time.perf_counter()
+        for b, (lo, hi) in enumerate(self.bands):
+            for ti, tfft in enumerate(self.tffts):
+                n_fft = int(t_obs / tfft)
+                injs = [S.Injection(f0=f0, tau=1.0 / (k * (self.n_values[ni] - 1) * f0 ** (self.n_values[ni] - 1)),
+                                    n=self.n_values[ni], amp=amp)
+                        for (bb, tt, ni, f0, k, amp) in inj if bb == b and tt == ti]
+                spec = S.MapSpec(f"b{b}t{tfft}", 3.0, tfft, lo, hi, n_fft, np.zeros(1), seed=seed * 100000 + b * 10 + ti,
+                                 injections=injs)
+                rp, bn, _ = S.gpu_peakmap(spec, dev)
+                self.peakmaps[(b, ti)] = (rp, bn)
+                P = int(bn.numel())
+                for ni, n in enumerate(self.n_values):
+                    k_max = (1.0 / tfft ** 2) / lo ** n
+                    kk = S.uniform_k(k_max, n_k)
+                    plan = fh.Plan(n, tfft, lo, hi, n_fft, kk)
+                    hmap = torch.empty((plan.n_k, plan.n_x0), dtype=torch.int32, device=dev)
+                    self.maps.append({"band": b, "ti": ti, "ni": ni, "n": n, "tfft": tfft, "f_min": lo, "f_max": hi,
+                                      "n_fft": n_fft, "k": kk, "plan": plan, "hmap": hmap, "P": P})
+                    self.U += P * n_k
+        torch.cuda.synchronize()
+        self.build_s = time.perf_counter() - t
+        self.peaks_total = sum(int(bn.numel()) for _, bn in self.peakmaps.values())
+        if log:
+            log(f"sweep: {len(self.maps)} maps, {len(self.peakmaps)} peakmaps, {self.peaks_total:.3e} peaks, "
+                f"U = {self.U:.3e} ({self.build_s:.1f} s to build)")
+        self.batch = fh.Batch([m["plan"] for m in self.maps],
+                              [self.peakmaps[(m["band"], m["ti"])] for m in self.maps],
+                              [m["hmap"] for m in self.maps])
+
+    def map_index(self, b, ti, ni):
+        return (b * len(self.tffts) + ti) * len(self.n_values) + ni
+
+    def destroy(self):
+        self.batch.destroy()
+
+
+def time_batch(sw: Sweep, steps: int = 5, warmup: int = 2, stream=None):
+    import torch
+    for _ in range(warmup):
+        sw.batch.launch(stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        sw.batch.launch(stream)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def time_plain(sw: Sweep):
+    import torch
+    sw.batch.launch_plain()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sw.batch.launch_plain()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def evaluate(sw: Sweep, net=None, sq=(8, 8), top_frac: float = 0.1, thresholds=(4.0, 5.0, 6.0)):
+    """Selection on every map (and the CNN's proposals when net is given);
+    efficiencies of both pipelines at each CR threshold."""
+    from . import fh
+    t0 = time.perf_counter()
+    cands = [fh.fh_select(m["plan"], m["hmap"], sq[0], sq[1], 3)[0] for m in sw.maps]
+    t_sel = time.perf_counter() - t0
+    props = None
+    t_prop = 0.0
+    n_tiles = 0
+    if net is not None:
+        t0 = time.perf_counter()
+        props = []
+        for m in sw.maps:
+            ta, tb = (m["plan"].n_k + 63) // 64, (m["plan"].n_x0 + 63) // 64
+            n_top = max(1, int(math.ceil(top_frac * ta * tb)))
+            n_tiles += ta * tb
+            props.append((set(fh.fh_propose(net, m["plan"], m["hmap"], n_top)[1]), tb))
+        t_prop = time.perf_counter() - t0
+    # injections' true cells, per map
+    truth: Dict[int, List] = {}
+    for (b, ti, ni, f0, k, amp) in sw.injections:
+        mi = sw.map_index(b, ti, ni)
+        m = sw.maps[mi]
+        info = m["plan"].info
+        col = (f0 ** (1.0 - m["n"]) - info.x0_min) / info.dx0
+        row = k / (m["k"][1] - m["k"][0])
+        truth.setdefault(mi, []).append((row, col))
+    res = {"select_s": t_sel, "propose_s": t_prop, "tiles": n_tiles, "curves": []}
+    noise_plain = {thr: 0 for thr in thresholds}
+    noise_learn = {thr: 0 for thr in thresholds}
+    det_plain = {thr: 0 for thr in thresholds}
+    det_learn = {thr: 0 for thr in thresholds}
+    for mi, cl in enumerate(cands):
+        tr = truth.get(mi, [])
+        keep = props[mi] if props is not None else None
+        for c in cl:
+            near = [math.hypot(c["row"] + 0.5 - r, c["col"] + 0.5 - x) for (r, x) in tr]
+            in_prop = keep is None or (c["row"] // 64) * keep[1] + (c["col"] // 64) in keep[0]
+            if not near or min(near) > 10.0:
+                for thr in thresholds:
+                    if c["cr"] >= thr:
+                        noise_plain[thr] += 1
+                        noise_learn[thr] += in_prop
+        for (r, x) in tr:
+            for thr in thresholds:
+                hits = [c for c in cl if c["cr"] >= thr and math.hypot(c["row"] + 0.5 - r, c["col"] + 0.5 - x) <= 3.0]
+                det_plain[thr] += bool(hits)
+                det_learn[thr] += any(keep is None or (c["row"] // 64) * keep[1] + (c["col"] // 64) in keep[0]
+                                      for c in hits)
+    n_inj = len(sw.injections)
+    for thr in thresholds:
+        res["curves"].append({"cr_thr": thr, "eff_plain": det_plain[thr] / n_inj,
+                              "eff_learned": det_learn[thr] / n_inj if props is not None else None,
+                              "noise_cands_plain": noise_plain[thr],
+                              "noise_cands_learned": noise_learn[thr] if props is not None else None})
+    return res
+
+
+def main():
+    import argparse
+    import json
+    import os
+    import sys
+
+    import torch
+    from . import fh
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--bands", type=int, default=30)
+    ap.add_argument("--weights", default=os.path.join(os.path.dirname(__file__), "trained", "tile_cnn.npy"))
+    a = ap.parse_args()
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)
+    dev = torch.device("cuda:0")
+    sw = Sweep(dev, n_bands=a.bands, log=log)
+    ms_b = time_batch(sw)
+    ms_p = time_plain(sw)
+    log(f"batched {ms_b:.3f} ms, plain {ms_p:.3f} ms")
+    net = fh.CNN(max_batch=256)
+    net.set_params(np.load(a.weights))
+    ev = evaluate(sw, net)
+    out = {"maps": len(sw.maps), "peakmaps": len(sw.peakmaps), "peaks": sw.peaks_total, "updates": sw.U,
+           "ms_batched": ms_b, "ms_plain": ms_p, "updates_per_s_batched": sw.U / (ms_b * 1e-3),
+           "updates_per_s_plain": sw.U / (ms_p * 1e-3), **ev}
+    print(json.dumps(out))
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(out, f, indent=1)
+    sw.destroy()
+
+
+if __name__ == "__main__":
+    main()

@@ -153,6 +153,49 @@ def make_peakmap(spec: MapSpec, chunk_rows: int = 2048) -> Peakmap:
                    n_fft=n_fft, n_f=n_f, sig_bins=sig)
 
 
+def gpu_peakmap(spec: MapSpec, dev, chunk_rows: int = 16384):
+    """The same peakmap model drawn on the GPU (torch, seeded by spec.seed; a
+    different random stream from make_peakmap): (row_ptr, bin) int32 tensors
+    on `dev` and the host copy of the signal bins.  For workloads too large to
+    draw on the host (the full sweep)."""
+    import torch
+    n_f, n_fft = spec.n_f, spec.n_fft
+    g = torch.Generator(device=dev)
+    g.manual_seed(int(spec.seed))
+    sig = signal_bins(spec)
+    sig_t = torch.from_numpy(sig).to(dev) if sig.size else None
+    counts, bins = [], []
+    for i0 in range(0, n_fft, chunk_rows):
+        i1 = min(n_fft, i0 + chunk_rows)
+        rows = i1 - i0
+        if spec.noiseless:
+            p = torch.zeros((rows, n_f), dtype=torch.float32, device=dev)
+        else:
+            p = -torch.log1p(-torch.rand((rows, n_f), generator=g, device=dev))
+        for q, inj in enumerate(spec.injections):
+            jj = sig_t[q, i0:i1]
+            ok = torch.nonzero(jj >= 0).squeeze(1)
+            if ok.numel() == 0:
+                continue
+            if spec.noiseless:
+                p[ok, jj[ok].long()] = inj.amp
+            else:
+                z = torch.randn((2, ok.numel()), generator=g, device=dev)
+                re = z[0] * math.sqrt(0.5) + math.sqrt(inj.amp)
+                im = z[1] * math.sqrt(0.5)
+                p[ok, jj[ok].long()] = re * re + im * im
+        c = p[:, 1:-1]
+        m = (c >= spec.theta) & (c > p[:, :-2]) & (c > p[:, 2:])
+        nz = torch.nonzero(m)
+        counts.append(torch.bincount(nz[:, 0], minlength=rows))
+        bins.append((nz[:, 1] + 1).to(torch.int32))
+    cnt = torch.cat(counts)
+    row_ptr = torch.zeros(n_fft + 1, dtype=torch.int64, device=dev)
+    row_ptr[1:] = torch.cumsum(cnt, 0)
+    assert int(row_ptr[-1].item()) < 2 ** 31
+    return row_ptr.to(torch.int32).contiguous(), torch.cat(bins).contiguous(), sig
+
+
 def full_peakmap(n_fft: int, n_f: int) -> Peakmap:
     """Every interior bin of every FFT is a peak (coverage counting)."""
     per = np.arange(1, n_f - 1, dtype=np.int32)
