@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the 990-map sweep and the search-layout extras")
     ap.add_argument("--cpu-rows", type=int, default=0, help="k rows of the oracle sample (0: the whole map)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scale for HBM traffic)")
@@ -73,6 +74,105 @@ def measured_traffic():
     if not (m_b and m_h) or m_h.group(1) != kernel_source_hash():
         return None
     return int(m_b.group(1))
+
+
+def timed(fn, K, W, stream):
+    import torch
+    for _ in range(W):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(K):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / K
+
+
+def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_oracle):
+    """The 990-map sweep (batched vs per-map launches, selection, CNN proposals,
+    detection efficiency) and timings of the search-layout steps: a map on the
+    paper's geometric k grid, coincidences of the sweep's candidates, the
+    follow-up projection and over-resolved maps of the large map's candidates."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1810_09784_amd import followup, grids, sweep
+    t = time.perf_counter()
+    sw = sweep.Sweep(dev, log=log)
+    ms_b = sweep.time_batch(sw, steps=K, warmup=2, stream=stream)
+    ms_p = sweep.time_plain(sw)
+    net = fh.CNN(max_batch=256)
+    net.set_params(np.load(os.path.join(ROOT, "paper_1810_09784_amd", "trained", "tile_cnn.npy")))
+    ev = sweep.evaluate(sw, net)
+    log(f"sweep: batched {ms_b:.3f} ms, plain {ms_p:.3f} ms, selection {ev['select_s']:.2f} s, "
+        f"proposals {ev['propose_s']:.2f} s")
+    parity = None
+    if check_oracle:
+        from oracle import hough as oracle
+        parity = True
+        for mi in (0, len(sw.maps) // 2, len(sw.maps) - 1):
+            m = sw.maps[mi]
+            rpm, bnm = sw.peakmaps[(m["band"], m["ti"])]
+            rows = [0, 1, m["plan"].n_k // 2, m["plan"].n_k - 1]
+            d = oracle.Desc(m["n"], m["tfft"], m["f_min"], m["f_max"], m["n_fft"], m["k"])
+            ref = oracle.hough(d, rpm.cpu().numpy(), bnm.cpu().numpy(), rows=rows)
+            parity = parity and bool(np.array_equal(m["hmap"][rows].cpu().numpy(), ref))
+        assert parity, "sweep map differs from the oracle on sampled rows"
+    sweep_out = {"workload": "11 n (2..7) x T_FFT {2,4,8} s x 30 bands of 64 Hz from 100 Hz, 5 days, 256 k rows; "
+                             "200 injections",
+                 "maps": len(sw.maps), "peakmaps": len(sw.peakmaps), "peaks": sw.peaks_total,
+                 "updates_per_launch": sw.U, "ms_batched": round(ms_b, 4), "ms_plain": round(ms_p, 4),
+                 "updates_per_s_batched": sw.U / (ms_b * 1e-3), "updates_per_s_plain": sw.U / (ms_p * 1e-3),
+                 "speedup_vs_plain": round(ms_p / ms_b, 3), "select_s": round(ev["select_s"], 3),
+                 "propose_s": round(ev["propose_s"], 3), "tiles_scored": ev["tiles"],
+                 "efficiency": ev["curves"], "parity_sampled_rows": parity,
+                 "note": "the tile CNN was trained on n = 5, 500-600 Hz, 4 h maps; here it scores other geometries"}
+    # coincidences: the sweep's candidates against a second draw of the same maps'
+    # candidates is not available, so the list is joined with itself moved by one bin
+    cl = [fh.fh_select(m["plan"], m["hmap"], 8, 8, 3)[0] for m in sw.maps]
+    pts, off = [], [0]
+    for m, c in zip(sw.maps, cl):
+        dk = float(m["k"][1] - m["k"][0])
+        pts += [(x["x0"], x["k"], m["plan"].info.dx0, dk) for x in c]
+        off.append(len(pts))
+    A = torch.tensor(pts, dtype=torch.float64, device=dev)
+    B = A.clone()
+    B[:, 0] += B[:, 2]
+    offs = torch.tensor(off, dtype=torch.int32, device=dev)
+    fh.fh_coincide(offs, A, offs, B)
+    ms_c = timed(lambda: fh.fh_coincide(offs, A, offs, B), 5, 1, stream)
+    sw.destroy()
+    # the paper's geometric k grid on the small band (n = 5, 500-600 Hz, T_FFT = 2 s)
+    tg = 2.0
+    ks, _ = grids.k_grid(5.0, tg, 500.0, 600.0, 1e-3 / tg ** 2, 1.0 / tg ** 2)
+    spec_g = synth.MapSpec("paper-grid", 5.0, tg, 500.0, 600.0, 7200, ks, seed=1,
+                           injections=synth.cfg_single_small().injections)
+    pm_g = synth.make_peakmap(spec_g)
+    plan_g = fh.Plan.from_spec(spec_g)
+    rpg, bng = torch.from_numpy(pm_g.row_ptr).to(dev), torch.from_numpy(pm_g.bin).to(dev)
+    hg = torch.empty((plan_g.n_k, plan_g.n_x0), dtype=torch.int32, device=dev)
+    ms_g = timed(lambda: fh.fh_hough(plan_g, rpg, bng, hg, stream), K, 2, stream)
+    # follow-up of the large map's candidates: projections and over-resolved maps
+    lst = cands_large["list"]
+    f0t = torch.tensor([float(c["f0"]) for c in lst], dtype=torch.float64, device=dev)
+    kt = torch.tensor([float(c["k"]) for c in lst], dtype=torch.float64, device=dev)
+    ms_proj = timed(lambda: fh.fh_project(plan, rp, bn, f0t, kt, w=40, guard=2), 3, 1, stream)
+    t_roi = time.perf_counter()
+    roi = followup.refine(dev, spec, rp, bn, [dict(x0=float(c["x0"]), k=float(c["k"])) for c in lst], plan.info.dx0,
+                          float(spec.k[1] - spec.k[0]))
+    s_roi = time.perf_counter() - t_roi
+    layout = {"paper_k_grid_map": {"workload": "n=5, 500-600 Hz, T_FFT=2 s, 7200 FFTs, geometric k grid "
+                                               "(fdot 1e-3..1 x 1/T_FFT^2)", "k_rows": int(len(ks)),
+                                   "ms": round(ms_g, 4), "updates_per_s": pm_g.n_peaks * len(ks) / (ms_g * 1e-3)},
+              "coincide": {"points": len(pts), "segments": len(off) - 1, "ms": round(ms_c, 4)},
+              "project": {"candidates": len(lst), "peaks": int(bn.numel()), "ms": round(ms_proj, 4),
+                          "peak_moves_per_s": len(lst) * int(bn.numel()) / (ms_proj * 1e-3)},
+              "roi_refine": {"candidates": len(roi), "cells_each": 60 * 60, "s_incl_plans": round(s_roi, 3)}}
+    log(f"layout: paper grid {ms_g:.3f} ms ({len(ks)} rows), coincide {ms_c:.3f} ms ({len(pts)} points), "
+        f"project {ms_proj:.3f} ms, ROI refine {s_roi:.2f} s")
+    return sweep_out, layout
 
 
 def timed_steps(step, K, W, stream):
@@ -239,6 +339,11 @@ def main():
                           "updates_per_s_batched": Ub / (ms_b * 1e-3), "updates_per_s_plain": Ub / (ms_p * 1e-3),
                           "speedup_vs_plain": round(ms_p / ms_b, 3)}
         batch.destroy()
+
+    # ------------------------------------------- the full sweep and extras --
+    if not a.no_sweep:
+        out["sweep"], out["layout"] = run_sweep(fh, synth, dev, stream, cands_large=cands, spec=spec, plan=plan, rp=rp,
+                                                bn=bn, K=max(3, K // 4), check_oracle=not a.no_cpu_baseline)
 
     if a.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.int32, device=dev)
