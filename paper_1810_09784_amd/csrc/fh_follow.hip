@@ -1,11 +1,12 @@
 // Follow-up projection (Sec. V on peakmaps): peaks moved by a candidate's
 // power-law drift, histogrammed around the candidate's initial bin, and the
-// critical ratio of that bin.  One work-group per candidate; threads take
-// FFTs, evaluate the drift once per FFT and add the FFT's moved peaks into
-// an LDS histogram.
+// critical ratio of that bin.  Work-groups per candidate split its FFTs;
+// threads take FFTs, evaluate the drift once per FFT and add the FFT's moved
+// peaks into an LDS histogram, which is added to the candidate's row.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
@@ -19,6 +20,9 @@ using gfo = __attribute__((address_space(1))) T*;
 constexpr int kProjThreads = 256;
 constexpr int kProjMaxW = 4096;
 
+// Grid: (candidates, splits); thread t of block y takes FFTs y * threads + t,
+// then every splits * threads, and the block adds its LDS histogram into the
+// candidate's row of hist (cleared beforehand).
 __global__ void __launch_bounds__(kProjThreads)
     k_project(const int32_t* row_ptr_, const int32_t* bin_, int n_peaks, int n_fft, int n_f, const double* T_,
               double n, double tfft, double f_min, const double* f0_, const double* k_, int w, int32_t* hist_) {
@@ -36,7 +40,8 @@ __global__ void __launch_bounds__(kProjThreads)
   const double a = (k * nm1) * pow(f0, nm1);
   const double e = 1.0 / nm1;
   const double b0 = floor((f0 - f_min) * tfft);
-  for (int i = threadIdx.x; i < n_fft; i += blockDim.x) {
+  const int stride = (int)(gridDim.y * blockDim.x);
+  for (int i = (int)(blockIdx.y * blockDim.x + threadIdx.x); i < n_fft; i += stride) {
     const double f = f0 / pow(1.0 + a * T[i], e);
     const double bi = floor((f - f_min) * tfft);
     // the drift in bins; |bi - b0| is below n_f + 1 whenever it matters
@@ -54,7 +59,13 @@ __global__ void __launch_bounds__(kProjThreads)
   }
   __syncthreads();
   gfo<int32_t> out = (gfo<int32_t>)hist_ + (size_t)c * nb;
-  for (int x = threadIdx.x; x < nb; x += blockDim.x) out[x] = hs[x];
+  for (int x = threadIdx.x; x < nb; x += blockDim.x)
+    if (hs[x]) __hip_atomic_fetch_add(out + x, hs[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void k_project_clear(int32_t* hist, long long n) {
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (long long)gridDim.x * blockDim.x)
+    ((gfo<int32_t>)hist)[x] = 0;
 }
 
 }  // namespace fh
@@ -71,7 +82,13 @@ extern "C" fh_status fh_project(fh_plan_t h, const fh_peaks* peaks, int32_t n_ca
   if (n_cand == 0) return FH_OK;
   hipStream_t s = (hipStream_t)stream;
   const int nb = 2 * w + 1;
-  hipLaunchKernelGGL(k_project, dim3((unsigned)n_cand), dim3(kProjThreads), nb * sizeof(int), s, peaks->row_ptr,
+  // enough work-groups to fill the chip: the FFTs of each candidate are split
+  const long long cells = (long long)n_cand * nb;
+  hipLaunchKernelGGL(k_project_clear, dim3((unsigned)std::min<long long>(1024, (cells + 255) / 256)), dim3(256), 0, s,
+                     hist, cells);
+  const int splits = std::max(1, std::min(std::max(1, p.desc.n_fft / kProjThreads), 2048 / std::max(1, n_cand)));
+  hipLaunchKernelGGL(k_project, dim3((unsigned)n_cand, (unsigned)splits), dim3(kProjThreads), nb * sizeof(int), s,
+                     peaks->row_ptr,
                      peaks->bin, (int)peaks->n_peaks, p.desc.n_fft, p.n_f, p.dT, p.desc.n, p.desc.tfft, p.desc.f_min,
                      f0, k, (int)w, hist);
   if (hipGetLastError() != hipSuccess) return FH_EDEVICE;
