@@ -104,7 +104,7 @@ def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_
     ms_b = sweep.time_batch(sw, steps=K, warmup=2, stream=stream)
     ms_p = sweep.time_plain(sw)
     net = fh.CNN(max_batch=256)
-    net.set_params(np.load(os.path.join(ROOT, "paper_1810_09784_amd", "trained", "tile_cnn.npy")))
+    net.set_params(np.load(os.path.join(ROOT, "paper_1810_09784_amd", "trained", "tile_cnn_sweep.npy")))
     ev = sweep.evaluate(sw, net)
     log(f"sweep: batched {ms_b:.3f} ms, plain {ms_p:.3f} ms, selection {ev['select_s']:.2f} s, "
         f"proposals {ev['propose_s']:.2f} s")
@@ -128,7 +128,7 @@ def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_
                  "speedup_vs_plain": round(ms_p / ms_b, 3), "select_s": round(ev["select_s"], 3),
                  "propose_s": round(ev["propose_s"], 3), "tiles_scored": ev["tiles"],
                  "efficiency": ev["curves"], "parity_sampled_rows": parity,
-                 "note": "the tile CNN was trained on n = 5, 500-600 Hz, 4 h maps; here it scores other geometries"}
+                 "note": "tile CNN trained on maps of this geometry drawn with other seeds (tile_cnn_sweep.npy)"}
     # coincidences: the sweep's candidates against a second draw of the same maps'
     # candidates is not available, so the list is joined with itself moved by one bin
     cl = [fh.fh_select(m["plan"], m["hmap"], 8, 8, 3)[0] for m in sw.maps]

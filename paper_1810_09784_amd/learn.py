@@ -211,3 +211,55 @@ def evaluate(dev, net, amps, n_noise: int, n_per_amp: int, seed: int, fap: float
         if log:
             log(f"a = {a}: plain {e_p:.3f}, learned {e_l:.3f}")
     return res
+
+
+def build_training_set_sweep(dev, n_peakmaps: int, seed: int, inj_per_map: int = 8, t_obs: float = 5 * 86400.0,
+                             n_k: int = 256, amp_lo: float = 0.5, amp_hi: float = 6.0, log=None):
+    """Tiles of the full sweep's geometry (bands of 64 Hz from 100 Hz, T_FFT 2,
+    4 or 8 s, n in 2..7, 5 days, 256 uniform k rows): per peakmap one (band,
+    T_FFT, n) with inj_per_map sources of that n on k rows 2..127 (f0 spread over
+    the band, a log-uniform in [amp_lo, amp_hi]); positives are the tiles
+    holding the sources' true cells, negatives as many random tiles holding
+    none.  Returns (tiles bf16 [N, 64, 64], labels float32 [N])."""
+    import torch
+    from . import fh, sweep
+    from . import synth as S
+    rng = np.random.default_rng(seed)
+    bands = sweep.band_edges(30)
+    tiles, labels = [], []
+    for q in range(n_peakmaps):
+        lo, hi = bands[int(rng.integers(len(bands)))]
+        tfft = float(rng.choice(sweep.TFFTS))
+        n = float(rng.choice(sweep.N_VALUES))
+        n_fft = int(t_obs / tfft)
+        kk = S.uniform_k((1.0 / tfft ** 2) / lo ** n, n_k)
+        edges = np.linspace(lo + 3.0, hi - 3.0, inj_per_map + 1)
+        injs, cells = [], []
+        for e in range(inj_per_map):
+            f0 = float(rng.uniform(edges[e], edges[e + 1]))
+            m = int(rng.integers(2, n_k // 2))
+            amp = math.exp(rng.uniform(math.log(amp_lo), math.log(amp_hi)))
+            injs.append(S.Injection(f0=f0, tau=1.0 / (kk[m] * (n - 1) * f0 ** (n - 1)), n=n, amp=amp))
+            cells.append((m, f0))
+        spec = S.MapSpec("train", n, tfft, lo, hi, n_fft, kk, seed=seed * 1000003 + q, injections=injs)
+        rp, bn, _ = S.gpu_peakmap(spec, dev)
+        plan = fh.Plan.from_spec(spec)
+        H = fh.fh_hough(plan, rp, bn)
+        tb = (plan.n_x0 + 63) // 64
+        ta = (plan.n_k + 63) // 64
+        pos = set()
+        for (m, f0) in cells:
+            col = int(math.floor((f0 ** (1.0 - n) - plan.info.x0_min) / plan.info.dx0))
+            col = min(max(col, 0), plan.n_x0 - 1)
+            pos.add((m // 64) * tb + col // 64)
+        neg_pool = [t for t in range(ta * tb) if t not in pos]
+        negs = list(rng.choice(neg_pool, size=min(len(pos), len(neg_pool)), replace=False)) if neg_pool else []
+        ids = sorted(pos) + [int(t) for t in negs]
+        org = torch.tensor([[64 * (t // tb), 64 * (t % tb)] for t in ids], dtype=torch.int32, device=dev)
+        tiles.append(fh.fh_tiles(H, org))
+        labels += [1.0] * len(pos) + [0.0] * len(negs)
+        if log and q % 100 == 0:
+            log(f"training maps {q}/{n_peakmaps}")
+    X = torch.cat(tiles, 0).contiguous()
+    y = torch.tensor(labels, dtype=torch.float32, device=dev)
+    return X, y

@@ -30,6 +30,9 @@ def main():
     ap.add_argument("--fap", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--weights", default=None, help="skip training, evaluate these parameters")
+    ap.add_argument("--geometry", default="small", choices=("small", "sweep"),
+                    help="small: the n = 5, 500-600 Hz maps; sweep: the full sweep's maps")
+    ap.add_argument("--sweep-maps", type=int, default=1250, help="training peakmaps of the sweep geometry")
     a = ap.parse_args()
     import torch
     from . import fh, learn
@@ -52,7 +55,11 @@ def main():
         th += [rng.normal(0, 0.1, 64), np.zeros(1)]
         net.set_params(np.concatenate(th))
         t = time.time()
-        X, y = learn.build_training_set(dev, a.pos, a.neg_maps, a.seed, amp_lo=a.amp_lo, amp_hi=a.amp_hi)
+        if a.geometry == "sweep":
+            X, y = learn.build_training_set_sweep(dev, a.sweep_maps, a.seed, amp_lo=a.amp_lo, amp_hi=a.amp_hi,
+                                                  log=log)
+        else:
+            X, y = learn.build_training_set(dev, a.pos, a.neg_maps, a.seed, amp_lo=a.amp_lo, amp_hi=a.amp_hi)
         torch.cuda.synchronize()
         log(f"training set: {X.shape[0]} tiles ({int(y.sum().item())} positive) in {time.time() - t:.1f} s")
         t = time.time()
@@ -67,8 +74,14 @@ def main():
         np.save(os.path.join(a.out, "tile_cnn.npy"), p)
         del X, y
     t = time.time()
-    amps = [float(x) for x in a.amps.split(",")]
-    res["evaluation"] = learn.evaluate(dev, net, amps, a.noise_maps, a.per_amp, a.seed + 100, a.fap, log=log)
+    if a.geometry == "sweep":
+        from . import sweep
+        sw = sweep.Sweep(dev, seed=a.seed + 100, log=log)
+        res["evaluation"] = sweep.evaluate(sw, net)
+        sw.destroy()
+    else:
+        amps = [float(x) for x in a.amps.split(",")]
+        res["evaluation"] = learn.evaluate(dev, net, amps, a.noise_maps, a.per_amp, a.seed + 100, a.fap, log=log)
     res["evaluation"]["seconds"] = time.time() - t
     with open(os.path.join(a.out, "learned.json"), "w") as f:
         json.dump(res, f, indent=1)

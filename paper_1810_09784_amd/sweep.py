@@ -132,7 +132,10 @@ def time_plain(sw: Sweep):
 def evaluate(sw: Sweep, net=None, sq=(8, 8), top_frac: float = 0.1, thresholds=(4.0, 5.0, 6.0)):
     """Selection on every map (and the CNN's proposals when net is given);
     efficiencies of both pipelines at each CR threshold."""
+    import torch
     from . import fh
+    sw.batch.launch()  # the maps of this evaluation
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     cands = [fh.fh_select(m["plan"], m["hmap"], sq[0], sq[1], 3)[0] for m in sw.maps]
     t_sel = time.perf_counter() - t0
@@ -199,7 +202,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
     ap.add_argument("--bands", type=int, default=30)
-    ap.add_argument("--weights", default=os.path.join(os.path.dirname(__file__), "trained", "tile_cnn.npy"))
+    ap.add_argument("--weights", default=os.path.join(os.path.dirname(__file__), "trained", "tile_cnn_sweep.npy"))
     a = ap.parse_args()
     log = lambda *x: print(*x, file=sys.stderr, flush=True)
     dev = torch.device("cuda:0")
