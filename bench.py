@@ -227,12 +227,13 @@ def main():
         e1.record(stream)
     torch.cuda.synchronize()
     cands = {}
+    SQ_K, SQ_X0, MIN_DK = 5, 5, 3  # candidate selection: 5 x 5 squares, a second candidate >= 3 k rows away
 
     def select(m, st):
-        # candidate selection: 5 x 5 squares, a second candidate >= 3 k rows away (Sec. IV)
-        cands["list"], cands["n"] = fh.fh_select(plan, m, 5, 5, 3, stream=st, as_dicts=False)
+        cands["list"], cands["n"] = fh.fh_select(plan, m, SQ_K, SQ_X0, MIN_DK, stream=st, as_dicts=False)
 
-    # (1) serial steps: fh_hough then fh_select on one stream, the host waiting for each step
+    # (1) the unfused path, serial: fh_hough then fh_select on one stream, the host
+    # waiting for each step
     def serial_step():
         fh.fh_hough(plan, rp, bn, hmap, stream)
         select(hmap, stream)
@@ -241,19 +242,16 @@ def main():
     # the Hough transform alone (rank build + tiles), same launch configuration
     ms_hough, _ = timed_steps(lambda: fh.fh_hough(plan, rp, bn, hmap, stream), K, 2, stream)
 
-    # (2) the timed run: steps pipelined over two map buffers and two streams.  Step k's
-    # fh_hough (stream A) runs while step k-1's fh_select (stream B, after A's event for
-    # that map) reads the other buffer, so the selection kernels and the host's part of
-    # the selection overlap the next transform.  Every step does the whole hot path.
+    # (2) the unfused path pipelined over two map buffers and two streams: step k's
+    # fh_hough (stream A) runs while step k-1's fh_select (stream B, after A's event
+    # for that map) reads the other buffer
     sel_stream = torch.cuda.Stream()
     hmaps = [hmap, torch.empty_like(hmap)]
     done = [torch.cuda.Event(), torch.cuda.Event()]
 
-    def pipelined(n, timed):
+    def unfused_pipelined(n):
         for k in range(n):
             j = k & 1
-            if timed:
-                fh.fh_plan_set_events(plan, ev[k][0], ev[k][1])
             fh.fh_hough(plan, rp, bn, hmaps[j], stream)
             done[j].record(stream)
             if k > 0:
@@ -261,25 +259,49 @@ def main():
                 select(hmaps[1 - j], sel_stream)
         sel_stream.wait_event(done[(n - 1) & 1])
         select(hmaps[(n - 1) & 1], sel_stream)
-        fh.fh_plan_set_events(plan, None, None)
 
-    pipelined(W, False)
+    unfused_pipelined(W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    unfused_pipelined(K)
+    torch.cuda.synchronize()
+    ms_unfused_pipe = (time.perf_counter() - t0) / K * 1e3
+
+    # (3) the timed run: fh_hough_select (the selection's row pass fused into the tile
+    # kernel's epilogue) on one stream, two plans of the same map alternating so that
+    # step k's square results are fetched on the host while step k+1 runs.  Every step
+    # does the whole hot path on its own map buffer.
+    plans2 = [plan, fh.Plan.from_spec(spec, tile=tile)]
+
+    def fused(n, timed):
+        for k in range(n):
+            j = k & 1
+            if timed:
+                fh.fh_plan_set_events(plans2[j], ev[k][0], ev[k][1])
+            fh.fh_hough_select(plans2[j], rp, bn, hmaps[j], SQ_K, SQ_X0, MIN_DK, stream=stream)
+            if k > 0:
+                cands["list"], cands["n"] = fh.fh_select_results(plans2[1 - j], as_dicts=False)
+        cands["list"], cands["n"] = fh.fh_select_results(plans2[(n - 1) & 1], as_dicts=False)
+        for p_ in plans2:
+            fh.fh_plan_set_events(p_, None, None)
+
+    fused(W, False)
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(stream)
     wall0 = time.perf_counter()
-    pipelined(K, True)
-    t1.record(sel_stream)
+    fused(K, True)
+    t1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms = t0.elapsed_time(t1) / K
     kern_ms = sum(e0.elapsed_time(e1) for e0, e1 in ev) / K
-    errs = fh.fh_device_errors(plan)
+    errs = fh.fh_device_errors(plans2[(K - 1) & 1])
     assert errs == 0, f"{errs} bad peaks"
     hmap = hmaps[(K - 1) & 1]  # the last step's map, checked against the oracle below
-    log(f"step {ms:.4f} ms pipelined (host wall {wall / K * 1e3:.4f} ms), {ms_serial:.4f} ms serial; "
-        f"hough {ms_hough:.4f} ms, tile kernel {kern_ms:.4f} ms, {cands['n']} candidates")
+    log(f"step {ms:.4f} ms fused (host wall {wall / K * 1e3:.4f} ms); unfused {ms_unfused_pipe:.4f} ms pipelined, "
+        f"{ms_serial:.4f} ms serial; hough {ms_hough:.4f} ms, tile kernel {kern_ms:.4f} ms, {cands['n']} candidates")
 
     # roofline of the tile kernel: algorithmic bytes = map store + peaks + CSR + tables, once
     map_bytes = 4 * plan.n_k * plan.n_x0
@@ -289,7 +311,8 @@ def main():
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(),
-            "kernel": f"fh::k_queue (persistent tile kernel, {plan.tile['threads']}-thread work-groups)",
+            "kernel": f"fh::k_queue (persistent tile kernel with the fused selection epilogue, "
+                      f"{plan.tile['threads']}-thread work-groups)",
             "kernel_ms": round(kern_ms, 5), "alg_bytes": alg_bytes}
 
     out = {
@@ -308,11 +331,13 @@ def main():
         "config": {"workload": "single map n=3, 200-1200 Hz, T_FFT=4 s, 43200 FFTs, 1024 k x 84000 x0",
                    "peaks": pm.n_peaks, "n_k": plan.n_k, "n_x0": plan.n_x0, "updates_per_step": U,
                    "tile": plan.tile, "parallelism": "1 GPU",
-                   "step": "fh_hough (rank build + tile kernel) + fh_select (5x5 squares, 2nd >= 3 rows), "
-                           "steps pipelined over two map buffers and two streams"},
-        "stages_ms": {"step_serial": round(ms_serial, 5), "hough": round(ms_hough, 5),
-                      "hough_tile_kernel": round(kern_ms, 5), "select_incl_host_serial": round(ms_serial - ms_hough, 5)},
-        "step_serial_updates_per_s": U / (ms_serial * 1e-3),
+                   "step": "fh_hough_select: rank build, tile kernel with the selection's row pass fused "
+                           "into its epilogue, split-tile selection pass, square reduction (5x5 squares, 2nd >= 3 "
+                           "rows), host CR; two plans alternate so the host finish overlaps the next step"},
+        "stages_ms": {"step_unfused_serial": round(ms_serial, 5), "step_unfused_pipelined": round(ms_unfused_pipe, 5),
+                      "hough": round(ms_hough, 5), "fused_tile_kernel": round(kern_ms, 5),
+                      "select_incl_host_serial": round(ms_serial - ms_hough, 5)},
+        "step_unfused_serial_updates_per_s": U / (ms_serial * 1e-3),
         "hough_only_updates_per_s": U / (ms_hough * 1e-3),
         "roofline": roof,
     }

@@ -175,6 +175,30 @@ typedef struct {
 fh_status fh_select(fh_plan_t plan, const int32_t* map, const fh_select_opts* opts, fh_candidate* out, int32_t cap,
                     int32_t* n_out, void* stream);
 
+/* The transform and the selection in one pass (Sec. IV: the Hough map, then
+ * its candidates): writes the same map as fh_hough and prepares the same
+ * candidates as fh_select with `opts` would, without reading the map back.
+ * The tile kernel adds each tile row's exact sums and largest count per
+ * column segment as it stores the counts (tiles split over several units:
+ * a short pass over their part of the map after the tile kernel); after the
+ * square reduction, the first column holding the largest count is searched
+ * in the two rows each square picks.  Asynchronous on
+ * `stream`: the square results are copied to pinned host memory owned by the
+ * plan and an event is recorded; fetch them with fh_select_results.  A new
+ * fh_hough_select (or an fh_select) of the same plan first waits for a
+ * pending one, whose results are then dropped if they were not fetched; the
+ * plan's scratch is shared, so one plan serves one such call at a time (use
+ * two plans of the same map description to overlap steps).  Errors: those of
+ * fh_hough and fh_select, FH_ENOMEM for the pinned buffer. */
+fh_status fh_hough_select(fh_plan_t plan, const fh_peaks* peaks, int32_t* map, const fh_select_opts* opts,
+                          void* stream);
+
+/* Candidates of the last fh_hough_select of this plan, as fh_select returns
+ * them (min(total, cap) records to `out` (HOST), the total to *n_out).  Waits
+ * for that call's event (not for the whole stream).  FH_EINVAL when no
+ * results are pending. */
+fh_status fh_select_results(fh_plan_t plan, fh_candidate* out, int32_t cap, int32_t* n_out);
+
 /* ---------------------------------------------------------- tile CNN --
  * A learned proposer of 64 x 64 map tiles (not in the paper, whose last
  * section only plans machine learning): tile (counts normalised by their map

@@ -187,6 +187,145 @@ struct WaveScratch {
 };
 static_assert(sizeof(WaveScratch) == 1040, "per-wave LDS scratch size is part of the LDS budget");
 
+
+// Fused candidate selection.  The epilogue produces each tile row's final
+// counts in ascending column runs per wavefront; SelRun adds them into the
+// selection's per-(row, column segment) partials: the exact sums of y and
+// y^2 and the largest count, packed as (count ^ 0x80000000) << 32 | ~0u (the
+// column of the best cells is found afterwards, only for the rows the square
+// reduction picks).  Lanes keep partials of the wave's current segment; a
+// segment's partials are reduced over the wave and added with 64-bit global
+// atomics when the segment ends inside the run or the run ends (a segment
+// cut by tile or run boundaries gets several additions).  Segment b covers
+// columns lo + floor(b (hi - lo) / sq) .. lo + floor((b + 1) (hi - lo) / sq) - 1.
+// A 64-bit value moved by one DPP pattern (0 where the pattern has no source).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long x) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)x, CTRL, ROWS, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(x >> 32), CTRL, ROWS, 0xf, false);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Sum and maximum over the wavefront (the scan pattern of wave_incl_scan; lane
+// 63 ends with the total), broadcast to every lane.
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long x) {
+  x += dpp_u64<0x111, 0xf>(x);
+  x += dpp_u64<0x112, 0xf>(x);
+  x += dpp_u64<0x114, 0xf>(x);
+  x += dpp_u64<0x118, 0xf>(x);
+  x += dpp_u64<0x142, 0xa>(x);
+  x += dpp_u64<0x143, 0xc>(x);
+  return readlane_u64(x, 63);
+}
+
+__device__ __forceinline__ unsigned long long wave_max_u64(unsigned long long x) {
+  unsigned long long y;
+  y = dpp_u64<0x111, 0xf>(x);
+  x = y > x ? y : x;
+  y = dpp_u64<0x112, 0xf>(x);
+  x = y > x ? y : x;
+  y = dpp_u64<0x114, 0xf>(x);
+  x = y > x ? y : x;
+  y = dpp_u64<0x118, 0xf>(x);
+  x = y > x ? y : x;
+  y = dpp_u64<0x142, 0xa>(x);
+  x = y > x ? y : x;
+  y = dpp_u64<0x143, 0xc>(x);
+  x = y > x ? y : x;
+  return readlane_u64(x, 63);
+}
+
+struct SelRun {
+  gptr<unsigned long long> out;  // this row's partials, [sq][3]
+  int sq, lo, hi;                // segments, analysed columns [lo, hi)
+  int b, s0, s1;                 // current segment and its columns [s0, s1); b < 0: none (wave-uniform)
+  unsigned long long sy, sy2;    // this lane's partials of segment b
+  int best;
+  int lane;
+
+  // counts are >= 0 (maps written by the tile kernel), so best = -1 means none yet
+  __device__ SelRun(const MapArgs& M, int row, int lane_)
+      : out((gptr<unsigned long long>)M.sel + (size_t)row * M.sel_sq * 3), sq(M.sel_sq), lo(M.sel_lo),
+        hi(M.sel_hi), b(-1), s0(0), s1(0), sy(0), sy2(0), best(-1), lane(lane_) {}
+
+  __device__ int edge(int q) const { return lo + (int)((long long)q * (hi - lo) / sq); }
+  // the segment holding column g (lo <= g < hi): the largest q with edge(q) <= g
+  __device__ int segment_of(int g) const { return (int)(((long long)(g - lo + 1) * sq - 1) / (hi - lo)); }
+
+  // Sums over four counts (pair sums fit 32 bits since counts <= n_fft < 2^31).
+  __device__ __forceinline__ void sums4(const v4i& v) {
+    sy += (unsigned long long)(unsigned)(v.x + v.y) + (unsigned long long)(unsigned)(v.z + v.w);
+    sy2 += (unsigned long long)(unsigned)v.x * (unsigned)v.x + (unsigned long long)(unsigned)v.y * (unsigned)v.y +
+           (unsigned long long)(unsigned)v.z * (unsigned)v.z + (unsigned long long)(unsigned)v.w * (unsigned)v.w;
+  }
+  // The four columns of a chunk with counts v, all counting.
+  __device__ __forceinline__ void add4_all(const v4i& v) {
+    sums4(v);
+    best = max(max(best, v.x), max(max(v.y, v.z), v.w));
+  }
+  // Only the chunk's columns (g .. g+3) inside [a, e) count: the others enter
+  // as 0 in the sums and as -1 (below every count) in the maximum.
+  __device__ __forceinline__ void add4(const v4i& v, int g, int a, int e) {
+    const v4i w = v4i{(g >= a && g < e) ? v.x : -1, (g + 1 >= a && g + 1 < e) ? v.y : -1,
+                      (g + 2 >= a && g + 2 < e) ? v.z : -1, (g + 3 >= a && g + 3 < e) ? v.w : -1};
+    best = max(max(best, w.x), max(max(w.y, w.z), w.w));
+    sums4(v4i{max(w.x, 0), max(w.y, 0), max(w.z, 0), max(w.w, 0)});
+  }
+  __device__ __forceinline__ void flush() {
+    if (b < 0) return;
+    const unsigned long long key =
+        best >= 0 ? ((unsigned long long)((unsigned)best ^ 0x80000000u) << 32) | 0xffffffffull : 0ull;
+    const unsigned long long s = wave_sum_u64(sy), s2 = wave_sum_u64(sy2);
+    const unsigned long long kmax = wave_max_u64(key);
+    if (lane == 0) {
+      gptr<unsigned long long> o = out + 3 * b;
+      __hip_atomic_fetch_add(o, (unsigned long long)s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(o + 1, (unsigned long long)s2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_max(o + 2, kmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    sy = 0;
+    sy2 = 0;
+    best = -1;
+    b = -1;
+  }
+  // One step of the wave's run: its chunks cover columns [ga, gb) (wave-
+  // uniform); this lane's chunk holds columns g .. g + 3 with counts v.
+  __device__ __forceinline__ void step(const v4i& v, int g, int ga, int gb) {
+    const int a = max(ga, lo), e = min(gb, hi);
+    if (a >= e) return;
+    if (b < 0 || a < s0 || a >= s1) {  // the step starts a segment
+      flush();
+      b = segment_of(a);
+      s0 = edge(b);
+      s1 = edge(b + 1);
+    }
+    if (e <= s1) {
+      if (a == ga && e == gb && gb - ga == 4 * kWave) add4_all(v);  // a full step inside the segment
+      else add4(v, g, a, e);
+      if (e == s1) flush();
+      return;
+    }
+    for (int x = a; x < e;) {  // segment boundaries inside the step
+      if (b < 0 || x < s0 || x >= s1) {
+        flush();
+        b = segment_of(x);
+        s0 = edge(b);
+        s1 = edge(b + 1);
+      }
+      const int y = min(e, s1);
+      add4(v, g, x, y);
+      if (y == s1) flush();
+      x = y;
+    }
+  }
+};
+
 // Epilogue helpers.  A tile row of the differential D is read in chunks of 4
 // columns (16-byte LDS accesses); pitch is a multiple of 4 and covers the pad
 // column W, so every chunk of a row lies inside it.
@@ -207,9 +346,11 @@ __device__ __forceinline__ int sum_chunks(const int* Drow, int k0, int k1, int l
 // columns below W go to `out`, and every chunk is left zero for the next
 // unit.  Plain stores go out as 16-byte chunks when `vec`; atomic adds (split
 // tiles) go through the row in LDS so that each instruction covers 64
-// consecutive columns.  Returns the carry after the last chunk.
+// consecutive columns.  `sr` (plain stores only): the fused selection of the
+// row, whose tile column 0 is map column gc0.  Returns the carry after the
+// last chunk.
 __device__ __forceinline__ int scan_chunks(int* Drow, int k0, int k1, int carry, int W, gptr<int> out, bool vec,
-                                           bool atomic, int lane) {
+                                           bool atomic, int lane, SelRun* sr = nullptr, int gc0 = 0) {
   for (int kb = k0; kb < k1; kb += kWave) {
     const int k = kb + lane;
     const bool in = k < k1;
@@ -237,8 +378,10 @@ __device__ __forceinline__ int scan_chunks(int* Drow, int k0, int k1, int carry,
         }
       }
     }
+    if (sr) sr->step(v, gc0 + 4 * k, gc0 + 4 * kb, gc0 + min(4 * min(kb + kWave, k1), W));
     carry += __builtin_amdgcn_readlane(incl, 63);
   }
+  if (sr) sr->flush();
   if (atomic) {  // this wave's own columns, in order (LDS is in order within a wave)
     for (int x = 4 * k0 + lane; x < 4 * k1; x += kWave) {
       const int y = Drow[x];
@@ -408,11 +551,50 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
   }
 }
 
+// Fused selection of the split tiles.  Their counts are final only when
+// every unit has added its part, so a pass after the tile kernel reads them
+// back from the map: grid (split tiles, kSelSplitParts), each work-group
+// takes a run of the tile's columns and its waves the tile's rows.
+constexpr int kSelSplitParts = 8;
+
+__device__ void sel_chunks(const MapArgs& M, const GMap& G, int r, int c0, int W, int k0, int k1, int lane) {
+  SelRun sr(M, r, lane);
+  const gptr<const int> row = (gptr<const int>)G.map + (size_t)r * M.n_x0 + c0;
+  for (int kb = k0; kb < k1; kb += kWave) {
+    const int k = kb + lane;
+    const int c = 4 * k;
+    v4i v = v4i{0, 0, 0, 0};
+    if (k < k1) {
+      if (c < W) v.x = row[c];
+      if (c + 1 < W) v.y = row[c + 1];
+      if (c + 2 < W) v.z = row[c + 2];
+      if (c + 3 < W) v.w = row[c + 3];
+    }
+    sr.step(v, c0 + c, c0 + 4 * kb, c0 + min(4 * min(kb + kWave, k1), W));
+  }
+  sr.flush();
+}
+
+__global__ void __launch_bounds__(256) k_select_split(MapArgs M, const int4* __restrict__ clears, int n_clears) {
+  const GMap G(M);
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  for (int c = blockIdx.x; c < n_clears; c += gridDim.x) {
+    const int tile = clears[c].y;
+    const int rt = tile / M.tiles_x, ct = tile - rt * M.tiles_x;
+    const int r0 = rt * M.rows, nrows = min(M.rows, M.n_k - r0);
+    const int c0 = ct * M.cols, W = min(M.cols, M.n_x0 - c0);
+    const int P4 = (W + 3) >> 2;
+    const int k0 = (int)((long long)P4 * blockIdx.y / gridDim.y);
+    const int k1 = (int)((long long)P4 * (blockIdx.y + 1) / gridDim.y);
+    for (int rl = wave; rl < nrows; rl += 4) sel_chunks(M, G, r0 + rl, c0, W, k0, k1, lane);
+  }
+}
+
 // One unit: tile `tile` of map M over FFTs [i_lo, i_hi); `atomic` when the
 // tile is split over several units (the map region was cleared beforehand).
 // `clean`: leading words of the differential tile at LDS offset `clean_at`
 // known to be zero (each epilogue leaves the rows it used zero).
-template <int THREADS, bool ALDS, int MODE>
+template <int THREADS, bool ALDS, int MODE, bool SEL>
 __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool atomic, bool load_a, char* smem,
                           int& clean, int& clean_at) {
   constexpr int NW = THREADS / kWave;
@@ -482,11 +664,17 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
     for (int rl = wave; rl < nrows; rl += NW) {
       gptr<int> out = G.map + (size_t)(r0 + rl) * M.n_x0 + c0;
       const bool vec = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
-      scan_chunks(D + rl * pitch, 0, P4, 0, W, out, vec, atomic, lane);
+      if (SEL && !atomic) {
+        SelRun sr(M, r0 + rl, lane);
+        scan_chunks(D + rl * pitch, 0, P4, 0, W, out, vec, false, lane, &sr, c0);
+      } else {
+        scan_chunks(D + rl * pitch, 0, P4, 0, W, out, vec, atomic, lane);
+      }
     }
   } else {
-    // few rows: all waves share each row, one run of chunks per wave
-    const int segc = (P4 + NW - 1) / NW;
+    // few rows: all waves share each row, one run of chunks per wave (with the
+    // fused selection, runs of whole 64-chunk steps)
+    const int segc = SEL ? (((P4 + NW - 1) / NW + kWave - 1) & ~(kWave - 1)) : (P4 + NW - 1) / NW;
     const int k0 = min(wave * segc, P4), k1 = min(k0 + segc, P4);
     for (int rl = 0; rl < nrows; ++rl) {
       int* Drow = D + rl * pitch;
@@ -497,7 +685,12 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
       for (int w = 0; w < wave; ++w) carry += wtot[w];
       gptr<int> out = G.map + (size_t)(r0 + rl) * M.n_x0 + c0;
       const bool vec = (reinterpret_cast<uintptr_t>(out) & 15) == 0;
-      scan_chunks(Drow, k0, k1, carry, W, out, vec, atomic, lane);
+      if (SEL && !atomic) {
+        SelRun sr(M, r0 + rl, lane);
+        scan_chunks(Drow, k0, k1, carry, W, out, vec, false, lane, &sr, c0);
+      } else {
+        scan_chunks(Drow, k0, k1, carry, W, out, vec, atomic, lane);
+      }
       __syncthreads();
     }
   }
@@ -508,7 +701,7 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
 // Persistent work-queue kernel: work-groups claim units (ordered longest
 // first) through an atomic counter until the queue is empty.  maps == nullptr:
 // every unit belongs to M0.
-template <int THREADS, bool ALDS, int MODE>
+template <int THREADS, bool ALDS, int MODE, bool SEL = false>
 __global__ void __launch_bounds__(THREADS) k_queue(MapArgs M0, const MapArgs* __restrict__ maps,
                                                   const Unit* __restrict__ units, int n_units, int* head) {
   extern __shared__ __align__(16) char smem[];
@@ -525,9 +718,10 @@ __global__ void __launch_bounds__(THREADS) k_queue(MapArgs M0, const MapArgs* __
     const int mi = u.x & ~kUnitAtomic;
     if (maps) {
       const MapArgs M = maps[mi];
-      tile_body<THREADS, ALDS, MODE>(M, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem, clean, clean_at);
+      tile_body<THREADS, ALDS, MODE, SEL>(M, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem, clean,
+                                          clean_at);
     } else {
-      tile_body<THREADS, ALDS, MODE>(M0, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem, clean,
+      tile_body<THREADS, ALDS, MODE, SEL>(M0, u.y, u.z, u.w, (u.x & kUnitAtomic) != 0, mi != loaded, smem, clean,
                                      clean_at);
     }
     loaded = mi;
@@ -544,6 +738,12 @@ __global__ void k_prologue(MapArgs M0, const MapArgs* __restrict__ maps, int n_m
   if (blockIdx.x == 0 && blockIdx.y == 0) {
     if (threadIdx.x == 0) *head = 0;
     for (int m = threadIdx.x; m < n_maps; m += blockDim.x) *(maps ? maps[m].err : M0.err) = 0;
+  }
+  if (M0.sel) {  // fused selection of a single-map launch: its partials to zero
+    const int nth = (int)(gridDim.x * gridDim.y * blockDim.x);
+    const int t = (int)((blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x);
+    const long long n_sel = (long long)M0.n_k * M0.sel_sq * 3;
+    for (long long x = t; x < n_sel; x += nth) ((gptr<unsigned long long>)M0.sel)[x] = 0;
   }
   for (int c = blockIdx.x; c < n_clears; c += gridDim.x) {
     const int4 e = clears[c];
@@ -714,11 +914,11 @@ __global__ void __launch_bounds__(kPrepWaves * 64) k_prepare_batch(const MapArgs
 
 static fh_status check_launch() { return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE; }
 
-template <int THREADS, bool ALDS, int MODE>
+template <int THREADS, bool ALDS, int MODE, bool SEL = false>
 static void set_lds_attr(int lds) {
   if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute((const void*)k_queue<THREADS, ALDS, MODE>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              lds);
+    (void)hipFuncSetAttribute((const void*)k_queue<THREADS, ALDS, MODE, SEL>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 template <int MODE>
@@ -740,24 +940,34 @@ int occupancy_grid(int threads, int lds_bytes, int n_units, int mode) {
   return (int)std::min<long long>(g, std::max(n_units, 1));
 }
 
-template <int THREADS, bool ALDS, int MODE>
+template <int THREADS, bool ALDS, int MODE, bool SEL>
 static fh_status launch_queue(const MapArgs& a, const Plan& p, hipStream_t s) {
-  set_lds_attr<THREADS, ALDS, MODE>(a.lds_bytes);
-  hipLaunchKernelGGL((k_queue<THREADS, ALDS, MODE>), dim3((unsigned)p.grid), dim3(THREADS), a.lds_bytes, s, a,
+  set_lds_attr<THREADS, ALDS, MODE, SEL>(a.lds_bytes);
+  hipLaunchKernelGGL((k_queue<THREADS, ALDS, MODE, SEL>), dim3((unsigned)p.grid), dim3(THREADS), a.lds_bytes, s, a,
                      (const MapArgs*)nullptr, (const Unit*)p.dUnits, (int)p.units.size(), p.dHead);
   return check_launch();
 }
 
-template <int MODE>
+// SEL: the tile kernel with the fused selection in its epilogue, a separate
+// instantiation so that the plain kernel keeps its register budget.
+template <int MODE, bool SEL>
 static fh_status launch_queue_mode(const MapArgs& a, const Plan& p, hipStream_t s) {
   const int th = p.tile.threads;
-  if (th == 1024) return a.a_lds ? launch_queue<1024, true, MODE>(a, p, s) : launch_queue<1024, false, MODE>(a, p, s);
-  if (th == 512) return a.a_lds ? launch_queue<512, true, MODE>(a, p, s) : launch_queue<512, false, MODE>(a, p, s);
-  return a.a_lds ? launch_queue<256, true, MODE>(a, p, s) : launch_queue<256, false, MODE>(a, p, s);
+  if (th == 1024)
+    return a.a_lds ? launch_queue<1024, true, MODE, SEL>(a, p, s) : launch_queue<1024, false, MODE, SEL>(a, p, s);
+  if (th == 512)
+    return a.a_lds ? launch_queue<512, true, MODE, SEL>(a, p, s) : launch_queue<512, false, MODE, SEL>(a, p, s);
+  return a.a_lds ? launch_queue<256, true, MODE, SEL>(a, p, s) : launch_queue<256, false, MODE, SEL>(a, p, s);
 }
 
-fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStream_t s) {
+fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStream_t s, const SelArgs* sel) {
   MapArgs a = p.args(pk, map);
+  if (sel) {
+    a.sel = sel->rows;
+    a.sel_sq = sel->sq;
+    a.sel_lo = sel->lo;
+    a.sel_hi = sel->hi;
+  }
   if (p.units.empty()) return FH_EINVAL;
   const int n_clears = (int)p.clears.size();
   hipLaunchKernelGGL(k_prologue, dim3((unsigned)std::max(1, std::min(n_clears, 1024)), kClearSplit), dim3(256), 0, s, a,
@@ -768,9 +978,19 @@ fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStrea
     if (check_launch() != FH_OK) return FH_EDEVICE;
   }
   if (p.ev_start && hipEventRecord(p.ev_start, s) != hipSuccess) return FH_EDEVICE;
-  const fh_status st = a.mode == kModeWhole ? launch_queue_mode<kModeWhole>(a, p, s)
-                                            : launch_queue_mode<kModeWindowed>(a, p, s);
+  fh_status st;
+  if (sel)
+    st = a.mode == kModeWhole ? launch_queue_mode<kModeWhole, true>(a, p, s)
+                              : launch_queue_mode<kModeWindowed, true>(a, p, s);
+  else
+    st = a.mode == kModeWhole ? launch_queue_mode<kModeWhole, false>(a, p, s)
+                              : launch_queue_mode<kModeWindowed, false>(a, p, s);
   if (st == FH_OK && p.ev_stop && hipEventRecord(p.ev_stop, s) != hipSuccess) return FH_EDEVICE;
+  if (st == FH_OK && sel && n_clears > 0) {
+    hipLaunchKernelGGL(k_select_split, dim3((unsigned)std::min(n_clears, 4096), kSelSplitParts), dim3(256), 0, s, a,
+                       (const int4*)p.dClears, n_clears);
+    return check_launch();
+  }
   return st;
 }
 

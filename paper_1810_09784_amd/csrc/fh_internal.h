@@ -42,6 +42,17 @@ struct MapArgs {
   int32_t pitch;           // LDS row pitch of the differential tile (ints)
   int32_t a_lds;           // A table staged in LDS
   int32_t lds_bytes;       // dynamic LDS of one tile
+  // fused candidate selection (single-map launches; sel == nullptr: none)
+  unsigned long long* sel; // [n_k][sel_sq][3] per row and column segment: Sy, Sy2, best-cell key
+  int32_t sel_sq;          // column segments (squares along x0)
+  int32_t sel_lo, sel_hi;  // analysed columns [sel_lo, sel_hi)
+};
+
+// Selection attached to a single-map launch: the row segment partials the
+// tile kernel adds into (cleared by the launch).
+struct SelArgs {
+  unsigned long long* rows;
+  int32_t sq, lo, hi;
 };
 
 // A unit of work: one tile over an FFT range.  x = map index | kUnitAtomic
@@ -79,6 +90,11 @@ struct Plan {
   int32_t* dHead = nullptr;
   unsigned long long* dSel = nullptr;  // fh_select scratch: row segment partials, then square results
   size_t sel_words = 0;               // its capacity in 64-bit words (grows on demand)
+  unsigned long long* hSq = nullptr;  // pinned host copy of the square results of fh_hough_select
+  size_t hsq_words = 0;
+  hipEvent_t ev_sel = nullptr;        // recorded after that copy
+  int32_t sel_pending = 0;            // results of an fh_hough_select not yet fetched
+  fh_select_opts sel_opts{};          // its options (col_hi resolved)
   int32_t grid = 0;  // persistent work-groups of a single-map launch
   int device = 0;
   int n_cu = 256;
@@ -96,7 +112,8 @@ void split_units(const Plan& p, int32_t mi, double target, std::vector<Unit>& un
                  std::vector<int4>& clears);
 
 // implemented in fh_hough.hip
-fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStream_t s);
+fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStream_t s,
+                       const SelArgs* sel = nullptr);
 int occupancy_grid(int threads, int lds_bytes, int n_units, int mode);
 
 }  // namespace fh

@@ -233,6 +233,7 @@ static fh_status validate_tile(const Plan& p, fh_tile_cfg* c) {
 }
 
 static void free_dev(Plan& p) {
+  if (p.sel_pending && p.ev_sel) (void)hipEventSynchronize(p.ev_sel);  // its copy still targets hSq
   if (p.dA) (void)hipFree(p.dA);
   if (p.dC) (void)hipFree(p.dC);
   if (p.dT) (void)hipFree(p.dT);
@@ -245,6 +246,11 @@ static void free_dev(Plan& p) {
   if (p.dSel) (void)hipFree(p.dSel);
   p.dSel = nullptr;
   p.sel_words = 0;
+  if (p.hSq) (void)hipHostFree(p.hSq);
+  p.hSq = nullptr;
+  p.hsq_words = 0;
+  if (p.ev_sel) (void)hipEventDestroy(p.ev_sel);
+  p.ev_sel = nullptr;
   p.dUnits = nullptr;
   p.dClears = nullptr;
   p.dHead = nullptr;

@@ -187,26 +187,74 @@ __global__ void __launch_bounds__(kSelThreads) k_select_squares(const unsigned l
   }
 }
 
+// Fused selection: its row partials carry the largest count of each (row,
+// segment) but not its column.  For the best and the second row of every
+// square, the first column of the row's segment holding that count (the
+// selection's tie rule) is searched here, every load of a thread in flight
+// at once.  Grid: (sq_k * sq_x0, 2).
+constexpr int kColThreads = 1024;
+constexpr int kColUnroll = 8;
+
+__global__ void __launch_bounds__(kColThreads) k_select_cols(const int32_t* map_, int n_x0, int col_lo, int col_hi,
+                                                              int sq_x0, unsigned long long* sq_out_) {
+  __shared__ int s_first[kColThreads / 64];
+  const int sqi = blockIdx.x, which = blockIdx.y, t = threadIdx.x;
+  gsel<unsigned long long> o = (gsel<unsigned long long>)sq_out_ + (size_t)sqi * kSqWords;
+  const unsigned long long key = o[2 + 2 * which];
+  if (!key) return;  // uniform over the work-group
+  const int y = (int)((unsigned)(key >> 32) ^ 0x80000000u);
+  const int r = (int)~(unsigned)(key & 0xffffffffu);
+  const int b = sqi % sq_x0;
+  const int W = col_hi - col_lo;
+  const int s0 = col_lo + (int)((long long)b * W / sq_x0);
+  const int s1 = col_lo + (int)((long long)(b + 1) * W / sq_x0);
+  const gsel<const int32_t> row = (gsel<const int32_t>)map_ + (size_t)r * n_x0;
+  int first = INT_MAX;
+  for (int c0 = s0; c0 < s1; c0 += kColThreads * kColUnroll) {
+    int v[kColUnroll];
+#pragma unroll
+    for (int u = 0; u < kColUnroll; ++u) {
+      const int c = c0 + u * kColThreads + t;
+      v[u] = c < s1 ? row[c] : -1;
+    }
+#pragma unroll
+    for (int u = kColUnroll - 1; u >= 0; --u)
+      if (v[u] == y) first = min(first, c0 + u * kColThreads + t);
+    if (__syncthreads_or(first != INT_MAX)) break;  // later columns are larger
+  }
+  for (int d = 32; d >= 1; d >>= 1) first = min(first, __shfl_xor(first, d));
+  if ((t & 63) == 0) s_first[t >> 6] = first;
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < kColThreads / 64; ++w) first = min(first, s_first[w]);
+    o[3 + 2 * which] = (unsigned long long)(unsigned)first;
+  }
+}
+
 }  // namespace fh
 
 using namespace fh;
 
-extern "C" fh_status fh_select(fh_plan_t h, const int32_t* map, const fh_select_opts* o, fh_candidate* out, int32_t cap,
-                               int32_t* n_out, void* stream) {
-  if (!h || !map || !o || !n_out || cap < 0 || (cap > 0 && !out)) return FH_EINVAL;
-  Plan& p = reinterpret_cast<Plan&>(*h);
-  const int n_k = p.desc.n_k;
-  const int col_lo = o->col_lo;
-  const int col_hi = o->col_hi > 0 ? o->col_hi : p.n_x0;
-  if (col_lo < 0 || col_hi > p.n_x0 || col_hi <= col_lo) return FH_EINVAL;
-  const int W = col_hi - col_lo;
-  if (o->sq_k < 1 || o->sq_k > n_k || o->sq_x0 < 1 || o->sq_x0 > std::min(W, kMaxSelectSegments)) return FH_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  const int sq_k = o->sq_k, sq_x0 = o->sq_x0;
-  const size_t row_words = (size_t)n_k * sq_x0 * 3;
-  const size_t n_sq = (size_t)sq_k * sq_x0;
-  const size_t need = row_words + n_sq * kSqWords;
-  if (need > p.sel_words) {  // grow the scratch (the previous select on this stream is complete)
+// Options checked against the plan; col_hi resolved.
+static fh_status check_opts(const Plan& p, const fh_select_opts* o, fh_select_opts* r) {
+  if (!o) return FH_EINVAL;
+  *r = *o;
+  r->col_hi = o->col_hi > 0 ? o->col_hi : p.n_x0;
+  if (r->col_lo < 0 || r->col_hi > p.n_x0 || r->col_hi <= r->col_lo) return FH_EINVAL;
+  const int W = r->col_hi - r->col_lo;
+  if (r->sq_k < 1 || r->sq_k > p.desc.n_k || r->sq_x0 < 1 || r->sq_x0 > std::min(W, kMaxSelectSegments))
+    return FH_EINVAL;
+  return FH_OK;
+}
+
+// Selection scratch of the plan: row partials (3 n_k sq_x0 words), then the
+// square results (kSqWords per square).  A pending fh_hough_select is waited
+// for before the scratch is touched.
+static fh_status sel_scratch(Plan& p, const fh_select_opts& o, unsigned long long** rows, unsigned long long** sq) {
+  if (p.sel_pending && hipEventSynchronize(p.ev_sel) != hipSuccess) return FH_EDEVICE;
+  const size_t row_words = (size_t)p.desc.n_k * o.sq_x0 * 3;
+  const size_t need = row_words + (size_t)o.sq_k * o.sq_x0 * kSqWords;
+  if (need > p.sel_words) {
     if (p.dSel) (void)hipFree(p.dSel);
     p.dSel = nullptr;
     p.sel_words = 0;
@@ -217,17 +265,16 @@ extern "C" fh_status fh_select(fh_plan_t h, const int32_t* map, const fh_select_
     }
     p.sel_words = need;
   }
-  unsigned long long* d_rows = p.dSel;
-  unsigned long long* d_sq = p.dSel + row_words;
-  hipLaunchKernelGGL(k_select_rows, dim3(n_k, sq_x0), dim3(kSelThreads), 0, s, map, p.n_x0, col_lo, col_hi, sq_x0,
-                     d_rows);
-  hipLaunchKernelGGL(k_select_squares, dim3(sq_k, sq_x0), dim3(kSelThreads), 0, s, d_rows, n_k, sq_k, sq_x0,
-                     o->min_dk, d_sq);
-  if (hipGetLastError() != hipSuccess) return FH_EDEVICE;
-  std::vector<unsigned long long> sq(n_sq * kSqWords);
-  if (hipMemcpyAsync(sq.data(), d_sq, sq.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return FH_EDEVICE;
+  *rows = p.dSel;
+  *sq = p.dSel + row_words;
+  return FH_OK;
+}
+
+// mu, sigma and CR of every square from its exact sums, and the candidates.
+static void emit_candidates(const Plan& p, const fh_select_opts& o, const unsigned long long* sq, fh_candidate* out,
+                            int32_t cap, int32_t* n_out) {
+  const int n_k = p.desc.n_k, sq_k = o.sq_k, sq_x0 = o.sq_x0;
+  const int W = o.col_hi - o.col_lo;
   int32_t total = 0;
   const double inv1n = 1.0 / (1.0 - p.desc.n);
   auto emit = [&](unsigned long long key, unsigned long long col, int sqi, int second, double mu, double sigma) {
@@ -235,7 +282,7 @@ extern "C" fh_status fh_select(fh_plan_t h, const int32_t* map, const fh_select_
     const int r = (int)~(unsigned)(key & 0xffffffffu);
     const int c = (int)col;
     const double cr = ((double)y - mu) / sigma;
-    if (!(cr >= o->cr_thr)) return;
+    if (!(cr >= o.cr_thr)) return;
     if (total < cap) {
       fh_candidate& e = out[total];
       std::memset(&e, 0, sizeof(e));
@@ -272,5 +319,84 @@ extern "C" fh_status fh_select(fh_plan_t h, const int32_t* map, const fh_select_
     }
   }
   *n_out = total;
+}
+
+extern "C" fh_status fh_select(fh_plan_t h, const int32_t* map, const fh_select_opts* o, fh_candidate* out, int32_t cap,
+                               int32_t* n_out, void* stream) {
+  if (!h || !map || !o || !n_out || cap < 0 || (cap > 0 && !out)) return FH_EINVAL;
+  Plan& p = reinterpret_cast<Plan&>(*h);
+  fh_select_opts r;
+  fh_status st = check_opts(p, o, &r);
+  if (st != FH_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long *d_rows, *d_sq;
+  st = sel_scratch(p, r, &d_rows, &d_sq);
+  if (st != FH_OK) return st;
+  hipLaunchKernelGGL(k_select_rows, dim3(p.desc.n_k, r.sq_x0), dim3(kSelThreads), 0, s, map, p.n_x0, r.col_lo,
+                     r.col_hi, r.sq_x0, d_rows);
+  hipLaunchKernelGGL(k_select_squares, dim3(r.sq_k, r.sq_x0), dim3(kSelThreads), 0, s, d_rows, p.desc.n_k, r.sq_k,
+                     r.sq_x0, r.min_dk, d_sq);
+  if (hipGetLastError() != hipSuccess) return FH_EDEVICE;
+  std::vector<unsigned long long> sq((size_t)r.sq_k * r.sq_x0 * kSqWords);
+  if (hipMemcpyAsync(sq.data(), d_sq, sq.size() * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FH_EDEVICE;
+  emit_candidates(p, r, sq.data(), out, cap, n_out);
+  return FH_OK;
+}
+
+extern "C" fh_status fh_hough_select(fh_plan_t h, const fh_peaks* pk, int32_t* map, const fh_select_opts* o,
+                                     void* stream) {
+  if (!h || !pk || !map || !pk->row_ptr || !o) return FH_EINVAL;
+  if (pk->n_peaks < 0 || pk->n_peaks >= (1LL << 31)) return FH_EINVAL;
+  if (pk->n_peaks > 0 && !pk->bin) return FH_EINVAL;
+  Plan& p = reinterpret_cast<Plan&>(*h);
+  fh_select_opts r;
+  fh_status st = check_opts(p, o, &r);
+  if (st != FH_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  unsigned long long *d_rows, *d_sq;
+  st = sel_scratch(p, r, &d_rows, &d_sq);
+  if (st != FH_OK) return st;
+  const size_t sq_words = (size_t)r.sq_k * r.sq_x0 * kSqWords;
+  if (sq_words > p.hsq_words) {
+    if (p.hSq) (void)hipHostFree(p.hSq);
+    p.hSq = nullptr;
+    p.hsq_words = 0;
+    const hipError_t e = hipHostMalloc((void**)&p.hSq, sq_words * sizeof(unsigned long long), hipHostMallocDefault);
+    if (e != hipSuccess) {
+      p.hSq = nullptr;
+      return e == hipErrorOutOfMemory ? FH_ENOMEM : FH_EDEVICE;
+    }
+    p.hsq_words = sq_words;
+  }
+  if (!p.ev_sel && hipEventCreateWithFlags(&p.ev_sel, hipEventDisableTiming) != hipSuccess) {
+    p.ev_sel = nullptr;
+    return FH_EDEVICE;
+  }
+  p.sel_pending = 0;
+  const SelArgs sa{d_rows, r.sq_x0, r.col_lo, r.col_hi};
+  st = launch_hough(p, *pk, map, s, &sa);
+  if (st != FH_OK) return st;
+  hipLaunchKernelGGL(k_select_squares, dim3(r.sq_k, r.sq_x0), dim3(kSelThreads), 0, s, d_rows, p.desc.n_k, r.sq_k,
+                     r.sq_x0, r.min_dk, d_sq);
+  hipLaunchKernelGGL(k_select_cols, dim3(r.sq_k * r.sq_x0, 2), dim3(kColThreads), 0, s, map, p.n_x0, r.col_lo, r.col_hi,
+                     r.sq_x0, d_sq);
+  if (hipGetLastError() != hipSuccess) return FH_EDEVICE;
+  if (hipMemcpyAsync(p.hSq, d_sq, sq_words * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipEventRecord(p.ev_sel, s) != hipSuccess)
+    return FH_EDEVICE;
+  p.sel_opts = r;
+  p.sel_pending = 1;
+  return FH_OK;
+}
+
+extern "C" fh_status fh_select_results(fh_plan_t h, fh_candidate* out, int32_t cap, int32_t* n_out) {
+  if (!h || !n_out || cap < 0 || (cap > 0 && !out)) return FH_EINVAL;
+  Plan& p = reinterpret_cast<Plan&>(*h);
+  if (!p.sel_pending) return FH_EINVAL;
+  if (hipEventSynchronize(p.ev_sel) != hipSuccess) return FH_EDEVICE;
+  emit_candidates(p, p.sel_opts, p.hSq, out, cap, n_out);
+  p.sel_pending = 0;
   return FH_OK;
 }

@@ -76,6 +76,8 @@ SIGNATURES = {
     "fh_plan_tables": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "fh_plan_destroy": (None, [C.c_void_p]),
     "fh_hough": (C.c_int, [C.c_void_p, C.POINTER(Peaks), C.c_void_p, C.c_void_p]),
+    "fh_hough_select": (C.c_int, [C.c_void_p, C.POINTER(Peaks), C.c_void_p, C.POINTER(SelectOpts), C.c_void_p]),
+    "fh_select_results": (C.c_int, [C.c_void_p, C.POINTER(Candidate), C.c_int32, C.POINTER(C.c_int32)]),
     "fh_device_errors": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_uint64)]),
     "fh_plan_set_events": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "fh_batch_create": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(Peaks), C.POINTER(C.c_void_p),
@@ -260,6 +262,37 @@ def fh_select(plan: Plan, hmap, sq_k: int, sq_x0: int, min_dk: int = 3, cr_thr: 
     n = C.c_int32()
     _check(lib().fh_select(plan.handle, C.c_void_p(_ptr(hmap)), C.byref(opts), buf, int(cap), C.byref(n),
                            _stream(stream)), "fh_select")
+    m = min(n.value, cap)
+    if not as_dicts:
+        import numpy as np
+        return np.ctypeslib.as_array(buf)[:m].copy(), int(n.value)
+    return [buf[i].as_dict() for i in range(m)], int(n.value)
+
+
+def fh_hough_select(plan: Plan, row_ptr, bin_, out, sq_k: int, sq_x0: int, min_dk: int = 3,
+                    cr_thr: float = -1e300, col_lo: int = 0, col_hi: int = 0, stream=None):
+    """The Hough map (into `out`, int32 [n_k, n_x0] CUDA) and the selection of
+    fh_select with these options in one pass, asynchronous on `stream`; the
+    candidates come from fh_select_results(plan)."""
+    import torch
+    assert out.dtype == torch.int32 and out.is_contiguous() and tuple(out.shape) == (plan.n_k, plan.n_x0)
+    if row_ptr.numel() != int(plan.info.n_fft) + 1:
+        raise ValueError("row_ptr must have n_fft + 1 entries")
+    pk = peaks_struct(row_ptr, bin_)
+    opts = SelectOpts(int(sq_k), int(sq_x0), int(min_dk), int(col_lo), int(col_hi), float(cr_thr))
+    _check(lib().fh_hough_select(plan.handle, C.byref(pk), C.c_void_p(_ptr(out)), C.byref(opts), _stream(stream)),
+           "fh_hough_select")
+    plan.sel_cap = 2 * int(sq_k) * int(sq_x0)
+    return out
+
+
+def fh_select_results(plan: Plan, cap: int = None, as_dicts: bool = True):
+    """Candidates of the plan's last fh_hough_select, as fh_select returns them."""
+    if cap is None:
+        cap = getattr(plan, "sel_cap", 1)
+    buf = (Candidate * max(1, cap))()
+    n = C.c_int32()
+    _check(lib().fh_select_results(plan.handle, buf, int(cap), C.byref(n)), "fh_select_results")
     m = min(n.value, cap)
     if not as_dicts:
         import numpy as np
