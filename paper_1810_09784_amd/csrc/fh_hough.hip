@@ -554,8 +554,10 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
 // Fused selection of the split tiles.  Their counts are final only when
 // every unit has added its part, so a pass after the tile kernel reads them
 // back from the map: grid (split tiles, kSelSplitParts), each work-group
-// takes a run of the tile's columns and its waves the tile's rows.
-constexpr int kSelSplitParts = 8;
+// takes a run of the tile's columns, cut into kSelSplitWaves pieces, and its
+// waves take the (row, piece) pairs.
+constexpr int kSelSplitParts = 16;
+constexpr int kSelSplitWaves = 4;
 
 __device__ void sel_chunks(const MapArgs& M, const GMap& G, int r, int c0, int W, int k0, int k1, int lane) {
   SelRun sr(M, r, lane);
@@ -575,7 +577,8 @@ __device__ void sel_chunks(const MapArgs& M, const GMap& G, int r, int c0, int W
   sr.flush();
 }
 
-__global__ void __launch_bounds__(256) k_select_split(MapArgs M, const int4* __restrict__ clears, int n_clears) {
+__global__ void __launch_bounds__(kSelSplitWaves * 64) k_select_split(MapArgs M, const int4* __restrict__ clears,
+                                                                        int n_clears) {
   const GMap G(M);
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   for (int c = blockIdx.x; c < n_clears; c += gridDim.x) {
@@ -583,10 +586,14 @@ __global__ void __launch_bounds__(256) k_select_split(MapArgs M, const int4* __r
     const int rt = tile / M.tiles_x, ct = tile - rt * M.tiles_x;
     const int r0 = rt * M.rows, nrows = min(M.rows, M.n_k - r0);
     const int c0 = ct * M.cols, W = min(M.cols, M.n_x0 - c0);
-    const int P4 = (W + 3) >> 2;
-    const int k0 = (int)((long long)P4 * blockIdx.y / gridDim.y);
-    const int k1 = (int)((long long)P4 * (blockIdx.y + 1) / gridDim.y);
-    for (int rl = wave; rl < nrows; rl += 4) sel_chunks(M, G, r0 + rl, c0, W, k0, k1, lane);
+    const long long P4 = (W + 3) >> 2;
+    const int pieces = (int)gridDim.y * kSelSplitWaves;
+    for (int it = wave; it < nrows * kSelSplitWaves; it += kSelSplitWaves) {
+      const int rl = it / kSelSplitWaves;
+      const int q = (int)blockIdx.y * kSelSplitWaves + it % kSelSplitWaves;
+      const int k0 = (int)(P4 * q / pieces), k1 = (int)(P4 * (q + 1) / pieces);
+      sel_chunks(M, G, r0 + rl, c0, W, k0, k1, lane);
+    }
   }
 }
 
@@ -987,8 +994,8 @@ fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStrea
                               : launch_queue_mode<kModeWindowed, false>(a, p, s);
   if (st == FH_OK && p.ev_stop && hipEventRecord(p.ev_stop, s) != hipSuccess) return FH_EDEVICE;
   if (st == FH_OK && sel && n_clears > 0) {
-    hipLaunchKernelGGL(k_select_split, dim3((unsigned)std::min(n_clears, 4096), kSelSplitParts), dim3(256), 0, s, a,
-                       (const int4*)p.dClears, n_clears);
+    const dim3 grid((unsigned)std::min(n_clears, 4096), kSelSplitParts);
+    hipLaunchKernelGGL(k_select_split, grid, dim3(kSelSplitWaves * 64), 0, s, a, (const int4*)p.dClears, n_clears);
     return check_launch();
   }
   return st;
