@@ -291,25 +291,52 @@ __global__ void __launch_bounds__(256) k_conv1_wgrad(const bf16_t* __restrict__ 
 }
 
 // ------------------------------------------------------------------ head --
-// feat[b][c] = mean over pixels of act4; logit = feat . w5 + b5.
-__global__ void __launch_bounds__(256) k_head_fwd(const bf16_t* __restrict__ act4, const float* __restrict__ w5,
-                                                  const float* __restrict__ b5, float* __restrict__ feat,
-                                                  float* __restrict__ logit) {
-  __shared__ float part[4][C4];
-  const int b = blockIdx.x, c = threadIdx.x & 63, q = threadIdx.x >> 6;
-  float s = 0.f;
-  for (int p = q; p < NPIX; p += 4) s += bf2f(act4[((size_t)b * NPIX + p) * C4 + c]);
-  part[q][c] = s;
+// feat[b][c] = mean over pixels of act4; logit = feat . w5 + b5.  One
+// work-group per tile: thread t reads channels 8 (t % 8) .. +7 of pixels
+// t / 8 + 128 m (16-byte loads, eight in flight), the 128 partial sums of a
+// channel are added in LDS in a fixed order.
+constexpr int kHeadThreads = 1024;
+constexpr int kHeadLanes = kHeadThreads / 8;  // pixel lanes
+constexpr int kHeadUnroll = 8;
+
+__global__ void __launch_bounds__(kHeadThreads) k_head_fwd(const bf16_t* __restrict__ act4,
+                                                           const float* __restrict__ w5, const float* __restrict__ b5,
+                                                           float* __restrict__ feat, float* __restrict__ logit) {
+  static_assert(C4 == 64 && NPIX % (kHeadLanes * kHeadUnroll) == 0, "head layout");
+  __shared__ float part[kHeadLanes][C4];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const int g = t & 7, pl = t >> 3;
+  const uint4* px = reinterpret_cast<const uint4*>(act4 + (size_t)b * NPIX * C4);  // 8 channels per uint4
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int p0 = pl; p0 < NPIX; p0 += kHeadLanes * kHeadUnroll) {
+    uint4 v[kHeadUnroll];
+#pragma unroll
+    for (int u = 0; u < kHeadUnroll; ++u) v[u] = px[(size_t)(p0 + u * kHeadLanes) * 8 + g];
+#pragma unroll
+    for (int u = 0; u < kHeadUnroll; ++u) {
+      const unsigned w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        s[2 * k] += __uint_as_float(w[k] << 16);
+        s[2 * k + 1] += __uint_as_float(w[k] & 0xffff0000u);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) part[pl][8 * g + k] = s[k];
   __syncthreads();
-  if (threadIdx.x < C4) {
-    const float f = (part[0][c] + part[1][c] + part[2][c] + part[3][c]) * (1.0f / NPIX);
-    feat[b * C4 + c] = f;
-    part[0][c] = f * w5[c];
+  __shared__ float red[C4];
+  if (t < C4) {
+    float f = 0.f;
+    for (int q = 0; q < kHeadLanes; ++q) f += part[q][t];
+    f *= 1.0f / NPIX;
+    feat[b * C4 + t] = f;
+    red[t] = f * w5[t];
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     float z = b5[0];
-    for (int e = 0; e < C4; ++e) z += part[0][e];
+    for (int e = 0; e < C4; ++e) z += red[e];
     logit[b] = z;
   }
 }
@@ -544,8 +571,8 @@ extern "C" fh_status fh_cnn_forward(fh_cnn_t h, const uint16_t* tiles, int32_t B
   if (st == FH_OK) st = launch_conv<C2, C3, false>(c->a2, c->w3, c->params + OFF_B3, nullptr, c->a3, B, s);
   if (st == FH_OK) st = launch_conv<C3, C4, false>(c->a3, c->w4, c->params + OFF_B4, nullptr, c->a4, B, s);
   if (st != FH_OK) return st;
-  hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(256), 0, s, c->a4, c->params + OFF_W5, c->params + OFF_B5, c->feat,
-                     c->logit);
+  hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(kHeadThreads), 0, s, c->a4, c->params + OFF_W5, c->params + OFF_B5,
+                     c->feat, c->logit);
   if (logits && hipMemcpyAsync(logits, c->logit, (size_t)B * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return FH_EDEVICE;
   c->last_batch = B;
