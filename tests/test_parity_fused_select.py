@@ -167,3 +167,56 @@ def test_fused_rejects_bad_options(dev):
             fh.fh_hough_select(plan, rp, bn, H, **kw)
     with pytest.raises(fh.FHError):
         fh.fh_select_results(plan)
+
+
+def test_fused_empty_peakmap_and_bad_bins(dev, oracle):
+    # no peaks at all: an all-zero map, sigma = 0 everywhere, no candidate;
+    # then bins outside [0, n_f): skipped in the map and counted as errors
+    import torch
+    from paper_1810_09784_amd import fh
+    from oracle import select as OS
+    rng = np.random.default_rng(77)
+    spec = S.cfg_tiny(rng, n_fft=64, n_f=40, n_k=20, n=3.0, kscale=0.05)
+    plan = fh.Plan.from_spec(spec, tile=dict(rows=4, cols=16, threads=256, mode=2, tsplit=4))
+    empty = S.Peakmap(row_ptr=np.zeros(spec.n_fft + 1, dtype=np.int32), bin=np.zeros(0, dtype=np.int32),
+                      n_fft=spec.n_fft, n_f=spec.n_f)
+    got_map, got, n = _fused(plan, empty, dev, (2, 3))
+    assert not got_map.any() and n == 0 and got == []
+    pm = S.random_peakmap(rng, spec.n_fft, spec.n_f, 0.1)
+    bins = pm.bin.copy()
+    bins[::7] = spec.n_f + 3  # out of range (ascending order is not kept for these FFTs)
+    bad = S.Peakmap(row_ptr=pm.row_ptr, bin=bins, n_fft=pm.n_fft, n_f=pm.n_f)
+    keep = bins < spec.n_f
+    counts = np.diff(pm.row_ptr)
+    fft_of = np.repeat(np.arange(spec.n_fft), counts)
+    rp_ok = np.zeros(spec.n_fft + 1, dtype=np.int32)
+    np.cumsum(np.bincount(fft_of[keep], minlength=spec.n_fft), out=rp_ok[1:])
+    ref_map = oracle.hough(oracle.Desc.from_spec(spec), rp_ok, bins[keep])
+    plan_w = fh.Plan.from_spec(spec, tile=dict(rows=4, cols=16, threads=256, mode=1, tsplit=4))
+    got_map, got, n = _fused(plan_w, bad, dev, (2, 3))  # whole-FFT mode: order within an FFT is irrelevant
+    assert np.array_equal(got_map, ref_map)
+    assert fh.fh_device_errors(plan_w) == int((~keep).sum())
+    nf, x0m, dx, nx = oracle.grid(oracle.Desc.from_spec(spec))
+    _compare(got, OS.select(ref_map, spec.k, x0m, dx, spec.n, 2, 3, 3))
+
+
+@pytest.mark.parametrize("cols", [1, 7, 300])
+def test_fused_one_column_segments(dev, oracle, cols):
+    # as many squares along x0 as analysed columns (every segment one column
+    # wide, boundaries inside every step), on narrow and wide tiles
+    from paper_1810_09784_amd import fh
+    from oracle import select as OS
+    rng = np.random.default_rng(5150 + cols)
+    spec = S.cfg_tiny(rng, n_fft=150, n_f=60, n_k=24, n=2.0, kscale=0.05)
+    pm = S.random_peakmap(rng, spec.n_fft, spec.n_f, 0.08)
+    plan = fh.Plan.from_spec(spec, tile=dict(rows=2, cols=cols, threads=512, mode=2, tsplit=2))
+    nx = plan.n_x0
+    lo, hi = 1, min(nx, 1 + 256)
+    d = oracle.Desc.from_spec(spec)
+    ref_map = oracle.hough(d, pm.row_ptr, pm.bin)
+    got_map, got, n = _fused(plan, pm, dev, (3, hi - lo), 2, -1e300, (lo, hi))
+    assert np.array_equal(got_map, ref_map)
+    nf, x0m, dx, _ = oracle.grid(d)
+    ref = OS.select(ref_map, spec.k, x0m, dx, spec.n, 3, hi - lo, 2, -1e300, lo, hi)
+    assert n == len(ref)
+    _compare(got, ref)
