@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_k_queue_large_map.md")
 KERNEL_SOURCES = ("paper_1810_09784_amd/csrc/fh_hough.hip", "paper_1810_09784_amd/csrc/fh_plan.cpp",
                   "paper_1810_09784_amd/csrc/fh_internal.h")
@@ -386,7 +387,7 @@ def main():
         whole = len(rows) == plan.n_k
         d = oracle.Desc.from_spec(spec)
         t = time.perf_counter()
-        ref = oracle.hough(d, pm.row_ptr, pm.bin, rows=None if whole else rows)
+        ref, in_grid = oracle.hough(d, pm.row_ptr, pm.bin, rows=None if whole else rows, return_pairs=True)
         dt_h = time.perf_counter() - t
         got = hmap.cpu().numpy() if whole else hmap[rows].cpu().numpy()
         parity = bool(np.array_equal(got, ref))
@@ -410,6 +411,21 @@ def main():
                                "cores": threads, "kind": "oracle", "sample": sample}
         out["parity_vs_oracle"] = {"checked": "whole map and candidates" if whole else f"{len(rows)} sampled rows",
                                    "equal": parity}
+        if whole:
+            # the work the map really contains: (peak, row) pairs whose clipped interval
+            # holds a column (counted by the oracle), each 2 FP64 fma + 2 FP64->int
+            # conversions and 2 LDS atomic edge updates in the tile kernel; roofs for
+            # those per-pair costs at the fused tile kernel's measured time
+            s_k = roof["kernel_ms"] * 1e-3
+            fp64 = 4.0 * in_grid / s_k / 1e12
+            lds = 2.0 * in_grid / s_k / 1e12
+            lds_peak = 32 * 256 * 2.4e9 / 1e12  # 32 lanes/clk/CU, 256 CUs, 2.4 GHz
+            out["work"] = {"in_grid_pairs": in_grid, "in_grid_fraction": round(in_grid / U, 5),
+                           "in_grid_pairs_per_s": in_grid / s_k,
+                           "fp64_roof": {"achieved": round(fp64, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                         "frac": round(fp64 / FP64_PEAK_TFLOPS, 4)},
+                           "lds_atomic_roof": {"achieved": round(lds, 3), "peak": round(lds_peak, 3),
+                                               "unit": "T atomic lane-ops/s", "frac": round(lds / lds_peak, 4)}}
         log(f"oracle: {len(rows)} rows in {dt_h:.2f} s + selection {dt_s:.2f} s on {threads} threads; "
             f"parity {parity}")
         assert parity, "GPU output differs from the oracle"

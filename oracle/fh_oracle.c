@@ -143,10 +143,12 @@ int orc_resolve(const orc_desc* d, int* n_f, double* x0_min, double* dx0, int* n
  * Direct Hough map for the rows listed in `rows` (n_rows of them; rows == NULL
  * means all n_k rows in order).  out is int32 [n_rows][n_x0], row-major, x0
  * ascending.  Peaks are a CSR by FFT: FFT i owns bin[row_ptr[i] .. row_ptr[i+1]).
- * A bin index outside [0, n_f) is skipped and counted in *n_bad.
+ * A bin index outside [0, n_f) is skipped and counted in *n_bad.  *n_pairs
+ * (if not NULL) gets the number of (row, peak) pairs whose clipped interval
+ * holds at least one column, the work the map really contains.
  */
-int orc_hough_rows(const orc_desc* d, const int32_t* row_ptr, const int32_t* bin, const int32_t* rows,
-                   int32_t n_rows, int32_t* out, int64_t* n_bad) {
+int orc_hough_rows_pairs(const orc_desc* d, const int32_t* row_ptr, const int32_t* bin, const int32_t* rows,
+                         int32_t n_rows, int32_t* out, int64_t* n_bad, int64_t* n_pairs) {
   int n_f, n_x0;
   double x0_min, dx0;
   if (orc_resolve(d, &n_f, &x0_min, &dx0, &n_x0) != ORC_OK) return ORC_EINVAL;
@@ -160,8 +162,8 @@ int orc_hough_rows(const orc_desc* d, const int32_t* row_ptr, const int32_t* bin
   orc_tables(d->n, d->tfft, d->f_min, n_f, x0_min, dx0, d->n_k, d->k, d->n_fft, d->t, A, C, T);
   int nr = rows ? n_rows : d->n_k;
   memset(out, 0, sizeof(int32_t) * (size_t)nr * (size_t)n_x0);
-  int64_t bad = 0;
-#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad)
+  int64_t bad = 0, pairs = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : bad, pairs)
   for (int q = 0; q < nr; ++q) {
     int r = rows ? rows[q] : q;
     int32_t* h = out + (size_t)q * (size_t)n_x0;
@@ -178,13 +180,20 @@ int orc_hough_rows(const orc_desc* d, const int32_t* row_ptr, const int32_t* bin
         double b_hi = floor(u_hi);
         if (b_lo < 0.0) b_lo = 0.0;
         if (b_hi > (double)(n_x0 - 1)) b_hi = (double)(n_x0 - 1);
+        pairs += b_lo <= b_hi;
         for (double b = b_lo; b <= b_hi; b += 1.0) h[(int64_t)b] += 1;
       }
     }
   }
   if (n_bad) *n_bad = bad;
+  if (n_pairs) *n_pairs = pairs;
   free(A); free(C); free(T);
   return ORC_OK;
+}
+
+int orc_hough_rows(const orc_desc* d, const int32_t* row_ptr, const int32_t* bin, const int32_t* rows,
+                   int32_t n_rows, int32_t* out, int64_t* n_bad) {
+  return orc_hough_rows_pairs(d, row_ptr, bin, rows, n_rows, out, n_bad, NULL);
 }
 
 int orc_hough(const orc_desc* d, const int32_t* row_ptr, const int32_t* bin, int32_t* out, int64_t* n_bad) {

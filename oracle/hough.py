@@ -47,6 +47,9 @@ def lib():
         ip = C.POINTER(C.c_int32)
         L.orc_hough_rows.restype = C.c_int
         L.orc_hough_rows.argtypes = [C.POINTER(OrcDesc), ip, ip, ip, C.c_int32, ip, C.POINTER(C.c_int64)]
+        L.orc_hough_rows_pairs.restype = C.c_int
+        L.orc_hough_rows_pairs.argtypes = [C.POINTER(OrcDesc), ip, ip, ip, C.c_int32, ip, C.POINTER(C.c_int64),
+                                           C.POINTER(C.c_int64)]
         L.orc_pair_interval.restype = C.c_int
         L.orc_pair_interval.argtypes = [C.POINTER(OrcDesc), C.c_int32, C.c_int32, C.c_int32, ip, ip]
         L.orc_threads.restype = C.c_int
@@ -132,8 +135,10 @@ def tables(d: Desc):
 
 
 def hough(d: Desc, row_ptr: np.ndarray, bin_: np.ndarray, rows: Optional[Sequence[int]] = None,
-          return_bad: bool = False):
-    """Direct Hough map, int32 [n_rows][n_x0] (all rows if rows is None)."""
+          return_bad: bool = False, return_pairs: bool = False):
+    """Direct Hough map, int32 [n_rows][n_x0] (all rows if rows is None);
+    with return_bad / return_pairs also the count of skipped bad peaks and of
+    (row, peak) pairs whose clipped interval holds a column."""
     nf, x0m, dx, nx = grid(d)
     if nf < 0 or nx <= 0:
         raise ValueError("invalid map description")
@@ -144,11 +149,13 @@ def hough(d: Desc, row_ptr: np.ndarray, bin_: np.ndarray, rows: Optional[Sequenc
     nr = d.n_k if rl is None else rl.shape[0]
     out = np.empty((nr, nx), dtype=np.int32)
     bad = C.c_int64(0)
-    st = lib().orc_hough_rows(C.byref(d.c), _iptr(rp), _iptr(bn), _iptr(rl), 0 if rl is None else nr,
-                              _iptr(out), C.byref(bad))
+    pairs = C.c_int64(0)
+    st = lib().orc_hough_rows_pairs(C.byref(d.c), _iptr(rp), _iptr(bn), _iptr(rl), 0 if rl is None else nr,
+                                    _iptr(out), C.byref(bad), C.byref(pairs))
     if st != 0:
         raise ValueError("oracle rejected the description")
-    return (out, bad.value) if return_bad else out
+    extra = ((bad.value,) if return_bad else ()) + ((pairs.value,) if return_pairs else ())
+    return (out,) + extra if extra else out
 
 
 def pair_interval(d: Desc, r: int, i: int, j: int):

@@ -236,6 +236,36 @@ def test_row_totals_equal_interval_widths(oracle):
         assert H[r].sum() == tot
 
 
+def test_in_grid_pair_count(oracle):
+    # The count of (row, peak) pairs whose clipped interval holds a column:
+    # at k = 0 every valid peak's image lies inside the x0 grid (the grid spans
+    # the band), so row 0 counts every peak; a row whose shift moves every image
+    # past x0_min counts none; any row equals the count of non-empty intervals
+    # of the exact-rational brute force on a tiny map.
+    rng = np.random.default_rng(12)
+    spec = S.cfg_tiny(rng, n_fft=12, n_f=14, n_k=5, n=3.0, tfft=2.0, f_min=300.0, kscale=0.5)
+    pm = S.random_peakmap(rng, spec.n_fft, spec.n_f, 0.3)
+    d = oracle.Desc.from_spec(spec)
+    H, pairs = oracle.hough(d, pm.row_ptr, pm.bin, rows=[0], return_pairs=True)
+    assert pairs == pm.n_peaks
+    A, Cr, T = oracle.tables(d)
+    nf, x0min, dx0, nx = oracle.grid(d)
+    big = np.array([1e9 * (A[0] + nx) / (Cr[1] * T[0]) * spec.k[1]])  # shift > A[0] + n_x0 columns at t_0
+    d_big = oracle.Desc(spec.n, spec.tfft, spec.f_min, spec.f_max, spec.n_fft, big)
+    assert oracle.hough(d_big, pm.row_ptr, pm.bin, return_pairs=True)[1] == 0
+    _, total = oracle.hough(d, pm.row_ptr, pm.bin, return_pairs=True)
+    Af = [Fraction(a) for a in A]
+    want = 0
+    for r in range(spec.n_k):
+        for i in range(spec.n_fft):
+            s = Fraction(Cr[r]) * Fraction(T[i])
+            for p in range(pm.row_ptr[i], pm.row_ptr[i + 1]):
+                j = int(pm.bin[p])
+                lo, hi = Af[j + 1] - s, Af[j] - s
+                want += any(lo < b + 1 and hi >= b for b in range(nx))
+    assert total == want
+
+
 def test_bad_bins_are_skipped_and_counted(oracle):
     rng = np.random.default_rng(9)
     spec = S.cfg_tiny(rng, n_fft=10, n_f=30, n_k=4)
