@@ -132,7 +132,7 @@ def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_
                  "note": "tile CNN trained on maps of this geometry drawn with other seeds (tile_cnn_sweep.npy)"}
     # coincidences: the sweep's candidates against a second draw of the same maps'
     # candidates is not available, so the list is joined with itself moved by one bin
-    cl = [fh.fh_select(m["plan"], m["hmap"], 8, 8, 3)[0] for m in sw.maps]
+    cl = sw.batch.select(8, 8, 3)
     pts, off = [], [0]
     for m, c in zip(sw.maps, cl):
         dk = float(m["k"][1] - m["k"][0])

@@ -260,6 +260,18 @@ fh_status fh_batch_launch(fh_batch_t batch, void* stream);
 fh_status fh_batch_launch_plain(fh_batch_t batch, void* stream);
 void fh_batch_destroy(fh_batch_t batch);
 
+/* Candidate selection (as fh_select, same options for every map; col_hi <= 0
+ * means each map's own n_x0) on every map of the batch, as written by its
+ * last launch: one row pass and one square reduction over all maps on
+ * `stream`, one copy of the square results, the CR finish on the host;
+ * synchronises `stream`.  Candidates go to `out` (HOST) map after map, at most
+ * cap in all; counts[i] (HOST [m]) gets map i's number with CR >= cr_thr and
+ * *n_out their sum.  The batch owns the scratch (grown on demand).  Errors:
+ * FH_EINVAL (options invalid for some map), FH_ERANGE (more than 2^31 row
+ * segments or squares), FH_ENOMEM, FH_EDEVICE. */
+fh_status fh_batch_select(fh_batch_t batch, const fh_select_opts* opts, fh_candidate* out, int32_t cap,
+                          int32_t* counts, int32_t* n_out, void* stream);
+
 /* One-shot convenience: create, launch on `stream`, synchronise, destroy. */
 fh_status fh_hough_batched(int32_t m, const fh_plan_t* plans, const fh_peaks* peaks, int32_t* const* maps,
                            void* stream);

@@ -1009,25 +1009,6 @@ using namespace fh;
 
 constexpr int kBatchWholeThreads = 512;  // batches of whole-FFT maps (measured best of 256/512/1024)
 
-struct fh_batch_s {
-  int32_t m = 0;
-  std::vector<const Plan*> plans;
-  std::vector<fh_peaks> peaks;
-  std::vector<int32_t*> maps;
-  std::vector<MapArgs> args;
-  MapArgs* d_maps = nullptr;
-  Unit* d_queue = nullptr;
-  int4* d_clears = nullptr;
-  int32_t* d_head = nullptr;
-  int32_t n_queue = 0, n_clears = 0;
-  int32_t grid = 0;
-  int32_t lds = 0;
-  int32_t threads = 256, mode = 0;  // persistent kernel: work-group size, compiled mode (0: per map)
-  hipStream_t cap = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-};
-
 static void batch_free(fh_batch_s* b) {
   if (!b) return;
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -1037,6 +1018,7 @@ static void batch_free(fh_batch_s* b) {
   if (b->d_queue) (void)hipFree(b->d_queue);
   if (b->d_clears) (void)hipFree(b->d_clears);
   if (b->d_head) (void)hipFree(b->d_head);
+  if (b->d_sel) (void)hipFree(b->d_sel);
   delete b;
 }
 

@@ -121,3 +121,26 @@ int occupancy_grid(int threads, int lds_bytes, int n_units, int mode);
 struct fh_plan_s {
   fh::Plan p;
 };
+
+// A batch of maps launched as one persistent, graph-captured queue
+// (fh_batch_*), and the scratch of its batched selection (fh_batch_select).
+struct fh_batch_s {
+  int32_t m = 0;
+  std::vector<const fh::Plan*> plans;
+  std::vector<fh_peaks> peaks;
+  std::vector<int32_t*> maps;
+  std::vector<fh::MapArgs> args;
+  fh::MapArgs* d_maps = nullptr;
+  fh::Unit* d_queue = nullptr;
+  int4* d_clears = nullptr;
+  int32_t* d_head = nullptr;
+  int32_t n_queue = 0, n_clears = 0;
+  int32_t grid = 0;
+  int32_t lds = 0;
+  int32_t threads = 256, mode = 0;  // persistent kernel: work-group size, compiled mode (0: per map)
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  unsigned long long* d_sel = nullptr;  // batched selection: map table, row partials, square results
+  size_t sel_bytes = 0;
+};

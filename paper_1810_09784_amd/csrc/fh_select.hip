@@ -140,11 +140,11 @@ __global__ void __launch_bounds__(kSelThreads) k_select_rows(const int32_t* map_
 // Per square (a, b): rows floor(a n_k / sq_k) .. floor((a+1) n_k / sq_k) - 1.
 // sq_out[(a * sq_x0 + b) * 6 + {0..5}] = Sy, Sy2, key1, col1, key2, col2 with
 // key = biased count << 32 | ~row (0 = no such row).  Grid: (sq_k, sq_x0).
-__global__ void __launch_bounds__(kSelThreads) k_select_squares(const unsigned long long* rows_, int n_k, int sq_k,
-                                                                 int sq_x0, int min_dk, unsigned long long* sq_out_) {
+__device__ void square_body(const unsigned long long* rows_, int n_k, int sq_k, int sq_x0, int min_dk, int a, int b,
+                            unsigned long long* sq_out_) {
   const gsel<const unsigned long long> rows = (gsel<const unsigned long long>)rows_;
   __shared__ int s_r1;
-  const int a = blockIdx.x, b = blockIdx.y, t = threadIdx.x;
+  const int t = threadIdx.x;
   const int r0 = (int)((long long)a * n_k / sq_k), r1 = (int)((long long)(a + 1) * n_k / sq_k);
   long long sy = 0, sy2 = 0;
   unsigned long long key = 0;
@@ -185,6 +185,75 @@ __global__ void __launch_bounds__(kSelThreads) k_select_squares(const unsigned l
     o[4] = key2;
     o[5] = col_of(key2);
   }
+}
+
+__global__ void __launch_bounds__(kSelThreads) k_select_squares(const unsigned long long* rows, int n_k, int sq_k,
+                                                                 int sq_x0, int min_dk, unsigned long long* sq_out) {
+  square_body(rows, n_k, sq_k, sq_x0, min_dk, blockIdx.x, blockIdx.y, sq_out);
+}
+
+// ------------------------------------------------------ batched selection --
+// One map of a batched selection: its rows are global rows [row0, row0 +
+// n_k) of the row partials, its squares global squares [sq0, sq0 + sq_k
+// sq_x0) of the square results.
+struct SelMap {
+  const int32_t* map;
+  int32_t n_k, n_x0, col_lo, col_hi;
+  int32_t row0, sq0;
+};
+
+// The map holding global index g, for a table ascending in `first`.
+template <typename F>
+__device__ __forceinline__ int find_map(const SelMap* maps, int m, int g, F first) {
+  int lo = 0, hi = m - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first(maps[mid]) <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Row pass over every map of the batch: one wavefront per (global row,
+// column segment), four per work-group.  Same sums, key and tie rule as
+// k_select_rows.
+constexpr int kBatchSelWaves = 4;
+
+__global__ void __launch_bounds__(kBatchSelWaves * 64) k_select_rows_batch(const SelMap* __restrict__ maps, int m,
+                                                                           long long n_items, int sq_x0,
+                                                                           unsigned long long* rows_out_) {
+  const int lane = threadIdx.x & 63;
+  const long long item = (long long)blockIdx.x * kBatchSelWaves + (threadIdx.x >> 6);
+  if (item >= n_items) return;  // uniform over the wavefront
+  const int grow = (int)(item / sq_x0), b = (int)(item % sq_x0);
+  const SelMap M = maps[find_map(maps, m, grow, [](const SelMap& x) { return x.row0; })];
+  const int r = grow - M.row0;
+  const int W = M.col_hi - M.col_lo;
+  const int s0 = M.col_lo + (int)((long long)b * W / sq_x0);
+  const int s1 = M.col_lo + (int)((long long)(b + 1) * W / sq_x0);
+  const gsel<const int32_t> row = (gsel<const int32_t>)M.map + (size_t)r * M.n_x0;
+  SegAcc acc;
+  for (int c = s0 + lane; c < s1; c += 64) acc.add(row[c], c);
+  unsigned long long key = acc.col >= 0 ? (biased(acc.best) << 32) | (unsigned)(~(unsigned)acc.col) : 0ull;
+  const long long sy = wave_sum_i64(acc.sy), sy2 = wave_sum_i64(acc.sy2);
+  key = wave_max_u64(key);
+  if (lane == 0) {
+    gsel<unsigned long long> o = (gsel<unsigned long long>)rows_out_ + (size_t)item * 3;
+    o[0] = (unsigned long long)sy;
+    o[1] = (unsigned long long)sy2;
+    o[2] = key;
+  }
+}
+
+// Square reduction over every map of the batch: one work-group per global square.
+__global__ void __launch_bounds__(kSelThreads) k_select_squares_batch(const SelMap* __restrict__ maps, int m, int sq_k,
+                                                                     int sq_x0, int min_dk,
+                                                                     const unsigned long long* rows,
+                                                                     unsigned long long* sq_out) {
+  const int g = blockIdx.x;
+  const SelMap M = maps[find_map(maps, m, g, [](const SelMap& x) { return x.sq0; })];
+  const int s = g - M.sq0;
+  square_body(rows + (size_t)M.row0 * sq_x0 * 3, M.n_k, sq_k, sq_x0, min_dk, s / sq_x0, s % sq_x0,
+              sq_out + (size_t)M.sq0 * kSqWords);
 }
 
 // Fused selection: its row partials carry the largest count of each (row,
@@ -398,5 +467,66 @@ extern "C" fh_status fh_select_results(fh_plan_t h, fh_candidate* out, int32_t c
   if (hipEventSynchronize(p.ev_sel) != hipSuccess) return FH_EDEVICE;
   emit_candidates(p, p.sel_opts, p.hSq, out, cap, n_out);
   p.sel_pending = 0;
+  return FH_OK;
+}
+
+extern "C" fh_status fh_batch_select(fh_batch_t b, const fh_select_opts* o, fh_candidate* out, int32_t cap,
+                                     int32_t* counts, int32_t* n_out, void* stream) {
+  if (!b || !o || !counts || !n_out || cap < 0 || (cap > 0 && !out)) return FH_EINVAL;
+  const int m = b->m;
+  std::vector<SelMap> tab(m);
+  std::vector<fh_select_opts> res(m);
+  long long rows = 0, squares = 0;
+  for (int i = 0; i < m; ++i) {
+    const Plan& p = *b->plans[i];
+    const fh_status st = check_opts(p, o, &res[i]);
+    if (st != FH_OK) return st;
+    tab[i] = SelMap{b->maps[i], p.desc.n_k, p.n_x0, res[i].col_lo, res[i].col_hi, (int32_t)rows, (int32_t)squares};
+    rows += p.desc.n_k;
+    squares += (long long)o->sq_k * o->sq_x0;
+  }
+  if (rows * o->sq_x0 >= (1LL << 31) || squares >= (1LL << 31)) return FH_ERANGE;
+  const size_t tab_bytes = ((sizeof(SelMap) * (size_t)m + 255) / 256) * 256;
+  const size_t row_words = (size_t)rows * o->sq_x0 * 3;
+  const size_t sq_words = (size_t)squares * kSqWords;
+  const size_t need = tab_bytes + 8 * (row_words + sq_words);
+  hipStream_t s = (hipStream_t)stream;
+  if (need > b->sel_bytes) {  // the previous batched selection has completed (this call synchronises)
+    if (b->d_sel) (void)hipFree(b->d_sel);
+    b->d_sel = nullptr;
+    b->sel_bytes = 0;
+    const hipError_t e = hipMalloc((void**)&b->d_sel, need);
+    if (e != hipSuccess) {
+      b->d_sel = nullptr;
+      return e == hipErrorOutOfMemory ? FH_ENOMEM : FH_EDEVICE;
+    }
+    b->sel_bytes = need;
+  }
+  SelMap* d_tab = reinterpret_cast<SelMap*>(b->d_sel);
+  unsigned long long* d_rows = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(b->d_sel) + tab_bytes);
+  unsigned long long* d_sq = d_rows + row_words;
+  if (hipMemcpyAsync(d_tab, tab.data(), sizeof(SelMap) * m, hipMemcpyHostToDevice, s) != hipSuccess)
+    return FH_EDEVICE;
+  const long long n_items = rows * o->sq_x0;
+  hipLaunchKernelGGL(k_select_rows_batch, dim3((unsigned)((n_items + kBatchSelWaves - 1) / kBatchSelWaves)),
+                     dim3(kBatchSelWaves * 64), 0, s, d_tab, m, n_items, o->sq_x0, d_rows);
+  hipLaunchKernelGGL(k_select_squares_batch, dim3((unsigned)squares), dim3(kSelThreads), 0, s, d_tab, m, o->sq_k,
+                     o->sq_x0, o->min_dk, d_rows, d_sq);
+  if (hipGetLastError() != hipSuccess) return FH_EDEVICE;
+  std::vector<unsigned long long> sq(sq_words);
+  if (hipMemcpyAsync(sq.data(), d_sq, sq_words * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FH_EDEVICE;
+  int32_t total = 0, written = 0;
+  for (int i = 0; i < m; ++i) {
+    int32_t n = 0;
+    const int32_t room = cap - written;
+    emit_candidates(*b->plans[i], res[i], sq.data() + (size_t)tab[i].sq0 * kSqWords, out ? out + written : nullptr,
+                    room, &n);
+    counts[i] = n;
+    written += std::min(n, room);
+    total += n;
+  }
+  *n_out = total;
   return FH_OK;
 }

@@ -87,6 +87,8 @@ SIGNATURES = {
     "fh_batch_destroy": (None, [C.c_void_p]),
     "fh_hough_batched": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p), C.POINTER(Peaks), C.POINTER(C.c_void_p),
                                    C.c_void_p]),
+    "fh_batch_select": (C.c_int, [C.c_void_p, C.POINTER(SelectOpts), C.POINTER(Candidate), C.c_int32,
+                                  C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_void_p]),
     "fh_select": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SelectOpts), C.c_void_p, C.c_int32,
                             C.POINTER(C.c_int32), C.c_void_p]),
     "fh_cnn_create": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p)]),
@@ -377,6 +379,26 @@ class Batch:
 
     def launch_plain(self, stream=None):
         _check(lib().fh_batch_launch_plain(self.handle, _stream(stream)), "fh_batch_launch_plain")
+
+    def select(self, sq_k: int, sq_x0: int, min_dk: int = 3, cr_thr: float = -1e300, col_lo: int = 0,
+               col_hi: int = 0, stream=None, as_dicts: bool = True):
+        """fh_batch_select: the candidates of every map (after the last launch), as
+        a list with one fh_select-style result per map."""
+        m = len(self._keep[0])
+        cap = 2 * int(sq_k) * int(sq_x0) * m
+        opts = SelectOpts(int(sq_k), int(sq_x0), int(min_dk), int(col_lo), int(col_hi), float(cr_thr))
+        buf = (Candidate * max(1, cap))()
+        counts = (C.c_int32 * m)()
+        n = C.c_int32()
+        _check(lib().fh_batch_select(self.handle, C.byref(opts), buf, cap, counts, C.byref(n), _stream(stream)),
+               "fh_batch_select")
+        out, at = [], 0
+        arr = np.ctypeslib.as_array(buf) if not as_dicts else None
+        for i in range(m):
+            c = int(counts[i])
+            out.append([buf[j].as_dict() for j in range(at, at + c)] if as_dicts else arr[at:at + c].copy())
+            at += c
+        return out
 
     def destroy(self):
         if self.handle:

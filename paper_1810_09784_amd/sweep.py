@@ -11,10 +11,10 @@ power a uniform in [amp_lo, amp_hi].
 
 One run: all maps in one batched persistent launch (captured graph), the
 plain selection (sq_k x sq_x0 squares, second candidate 3 rows away) on
-every map, the tile CNN's scores of every 64 x 64 tile and its top tiles,
-and the detection efficiency of the plain selection and of the selection
-restricted to the proposed tiles (a detection: a candidate with CR >= thr
-within 3 bins of the injection's true cell in its own map).  Candidates
+every map in one batched pass, the tile CNN's scores of every 64 x 64 tile
+and its top tiles, and the detection efficiency of the plain selection and
+of the selection restricted to the proposed tiles (a detection: a candidate
+with CR >= thr within 3 bins of the injection's true cell in its own map).  Candidates
 farther than 10 bins from every injection of their map count as noise.
 """
 from __future__ import annotations
@@ -137,7 +137,7 @@ def evaluate(sw: Sweep, net=None, sq=(8, 8), top_frac: float = 0.1, thresholds=(
     sw.batch.launch()  # the maps of this evaluation
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    cands = [fh.fh_select(m["plan"], m["hmap"], sq[0], sq[1], 3)[0] for m in sw.maps]
+    cands = sw.batch.select(sq[0], sq[1], 3)  # every map in one batched pass
     t_sel = time.perf_counter() - t0
     props = None
     t_prop = 0.0
