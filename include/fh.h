@@ -241,6 +241,9 @@ fh_status fh_tiles(const int32_t* map, int32_t n_k, int32_t n_x0, const int32_t*
 fh_status fh_propose(fh_cnn_t net, fh_plan_t plan, const int32_t* map, float* scores, int32_t n_top,
                      int32_t* tile_ids, void* stream);
 
+/* Declared with the batches below: fh_batch_propose, fh_propose over every
+ * map of a batch. */
+
 /* ----------------------------------------------------------- batching --
  * Many maps of uneven size in one persistent launch: every tile of every map
  * goes into one work queue, longest (estimated) first, claimed by a grid of
@@ -271,6 +274,19 @@ void fh_batch_destroy(fh_batch_t batch);
  * segments or squares), FH_ENOMEM, FH_EDEVICE. */
 fh_status fh_batch_select(fh_batch_t batch, const fh_select_opts* opts, fh_candidate* out, int32_t cap,
                           int32_t* counts, int32_t* n_out, void* stream);
+
+/* fh_propose on every map of the batch (as written by its last launch) with
+ * one network: row statistics of all maps in one launch, then the tiles of
+ * all maps in the network's batches (tiles of several maps share a forward
+ * pass; each tile's score does not depend on its batch-mates), one copy of the
+ * scores.  scores: DEVICE float [sum of the maps' tile counts], map after
+ * map, each map's tiles in fh_propose's order.  n_top: HOST [m], each within
+ * [0, that map's tile count].  tile_ids: HOST, sum of n_top, map after map,
+ * each map's best tiles first (ties: lower tile index first).  Synchronises
+ * `stream`.  Errors: FH_EINVAL, FH_ERANGE (2^31 rows or tiles), FH_ENOMEM,
+ * FH_EDEVICE. */
+fh_status fh_batch_propose(fh_cnn_t net, fh_batch_t batch, float* scores, const int32_t* n_top, int32_t* tile_ids,
+                           void* stream);
 
 /* One-shot convenience: create, launch on `stream`, synchronise, destroy. */
 fh_status fh_hough_batched(int32_t m, const fh_plan_t* plans, const fh_peaks* peaks, int32_t* const* maps,

@@ -437,6 +437,73 @@ __global__ void __launch_bounds__(256) k_gather(const int32_t* __restrict__ map,
   }
 }
 
+// Batched proposals: one map of the batch.  Its rows are global rows [row0,
+// row0 + n_k) of the row statistics, its tiles global tiles [tile0, tile0 +
+// ta * tb), tile l at origin ((l / tb) * HW, (l % tb) * HW).
+struct PMap {
+  const int32_t* map;
+  int32_t n_k, n_x0, tb;
+  int32_t row0, tile0;
+};
+
+template <typename F>
+__device__ __forceinline__ int find_pmap(const PMap* maps, int m, int g, F first) {
+  int lo = 0, hi = m - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (first(maps[mid]) <= g) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Row statistics of every map of the batch: one work-group per global row.
+__global__ void __launch_bounds__(256) k_row_stats_batch(const PMap* __restrict__ maps, int m,
+                                                         float* __restrict__ mean, float* __restrict__ istd) {
+  const int g = blockIdx.x;
+  const PMap M = maps[find_pmap(maps, m, g, [](const PMap& x) { return x.row0; })];
+  const int r = g - M.row0;
+  __shared__ long long s1[256], s2[256];
+  long long a = 0, q = 0;
+  for (int c = threadIdx.x; c < M.n_x0; c += 256) {
+    const long long v = M.map[(size_t)r * M.n_x0 + c];
+    a += v;
+    q += v * v;
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = q;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      s1[threadIdx.x] += s1[threadIdx.x + o];
+      s2[threadIdx.x] += s2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double mu = (double)s1[0] / M.n_x0;
+    const double var = (double)s2[0] / M.n_x0 - mu * mu;
+    mean[g] = (float)mu;
+    istd[g] = var > 0 ? (float)(1.0 / sqrt(var)) : 0.f;
+  }
+}
+
+// Tiles t0 .. t0 + gridDim.x - 1 of the batch (global tile indices), as k_gather.
+__global__ void __launch_bounds__(256) k_gather_batch(const PMap* __restrict__ maps, int m, int t0,
+                                                      const float* __restrict__ mean, const float* __restrict__ istd,
+                                                      bf16_t* __restrict__ tiles) {
+  const int g = t0 + blockIdx.x;
+  const PMap M = maps[find_pmap(maps, m, g, [](const PMap& x) { return x.tile0; })];
+  const int l = g - M.tile0;
+  const int r0 = (l / M.tb) * HW, c0 = (l % M.tb) * HW;
+  for (int e = threadIdx.x; e < NPIX; e += 256) {
+    const int y = e / HW, x = e % HW, r = r0 + y, c = c0 + x;
+    float v = 0.f;
+    if (r < M.n_k && c < M.n_x0)
+      v = ((float)M.map[(size_t)r * M.n_x0 + c] - mean[M.row0 + r]) * istd[M.row0 + r];
+    tiles[(size_t)blockIdx.x * NPIX + e] = f2bf(v);
+  }
+}
+
 }  // namespace cnn
 }  // namespace fh
 
@@ -453,6 +520,8 @@ struct fh_cnn_s {
   float *row_mean = nullptr, *row_istd = nullptr;
   int row_cap = 0;
   int2* origins = nullptr;
+  PMap* ptab = nullptr;  // batched proposals: the map table
+  int ptab_cap = 0;
   int steps = 0;
   int last_batch = 0;
 };
@@ -468,7 +537,7 @@ void cnn_free(fh_cnn_s* c) {
   if (!c) return;
   void* ptrs[] = {c->params, c->grads, c->m1,  c->m2,   c->w2,    c->w3,    c->w4, c->w2t, c->w3t, c->w4t, c->x,
                   c->a1,     c->a2,    c->a3,  c->a4,   c->d1,    c->d2,    c->d3, c->d4,  c->feat, c->logit,
-                  c->loss,   c->row_mean, c->row_istd, c->origins};
+                  c->loss,   c->row_mean, c->row_istd, c->origins, c->ptab};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
@@ -665,5 +734,68 @@ extern "C" fh_status fh_propose(fh_cnn_t h, fh_plan_t ph, const int32_t* map, fl
   for (int i = 0; i < n_tiles; ++i) idx[i] = i;
   std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return sc[x] > sc[y]; });
   for (int i = 0; i < n_top; ++i) tile_ids[i] = idx[i];
+  return FH_OK;
+}
+
+extern "C" fh_status fh_batch_propose(fh_cnn_t h, fh_batch_t b, float* scores, const int32_t* n_top,
+                                      int32_t* tile_ids, void* stream) {
+  if (!h || !b || !scores || !n_top) return FH_EINVAL;
+  fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);
+  const int m = b->m;
+  std::vector<PMap> tab(m);
+  long long rows = 0, tiles = 0, picks = 0;
+  for (int i = 0; i < m; ++i) {
+    const fh::Plan& p = *b->plans[i];
+    const int n_k = p.desc.n_k, n_x0 = p.n_x0;
+    const int ta = (n_k + HW - 1) / HW, tb = (n_x0 + HW - 1) / HW;
+    if (n_top[i] < 0 || n_top[i] > ta * tb) return FH_EINVAL;
+    tab[i] = PMap{b->maps[i], n_k, n_x0, tb, (int32_t)rows, (int32_t)tiles};
+    rows += n_k;
+    tiles += (long long)ta * tb;
+    picks += n_top[i];
+  }
+  if (rows >= (1LL << 31) || tiles >= (1LL << 31)) return FH_ERANGE;
+  if (picks > 0 && !tile_ids) return FH_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (c->row_cap < rows) {
+    if (c->row_mean) (void)hipFree(c->row_mean);
+    if (c->row_istd) (void)hipFree(c->row_istd);
+    c->row_mean = c->row_istd = nullptr;
+    c->row_cap = 0;
+    if (!dalloc(&c->row_mean, (size_t)rows) || !dalloc(&c->row_istd, (size_t)rows)) return FH_ENOMEM;
+    c->row_cap = (int)rows;
+  }
+  if (c->ptab_cap < m) {
+    if (c->ptab) (void)hipFree(c->ptab);
+    c->ptab = nullptr;
+    c->ptab_cap = 0;
+    if (!dalloc(&c->ptab, (size_t)m)) return FH_ENOMEM;
+    c->ptab_cap = m;
+  }
+  if (hipMemcpyAsync(c->ptab, tab.data(), sizeof(PMap) * m, hipMemcpyHostToDevice, s) != hipSuccess)
+    return FH_EDEVICE;
+  hipLaunchKernelGGL(k_row_stats_batch, dim3((unsigned)rows), dim3(256), 0, s, c->ptab, m, c->row_mean, c->row_istd);
+  // chunks of the network's batch; every step is ordered on `stream`
+  for (long long t0 = 0; t0 < tiles; t0 += c->max_batch) {
+    const int B = (int)std::min<long long>(c->max_batch, tiles - t0);
+    hipLaunchKernelGGL(k_gather_batch, dim3(B), dim3(256), 0, s, c->ptab, m, (int)t0, c->row_mean, c->row_istd, c->x);
+    const fh_status st = fh_cnn_forward(h, c->x, B, scores + t0, stream);
+    if (st != FH_OK) return st;
+  }
+  std::vector<float> sc((size_t)tiles);
+  if (hipMemcpyAsync(sc.data(), scores, sizeof(float) * (size_t)tiles, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FH_EDEVICE;
+  long long at = 0;
+  std::vector<int32_t> idx;
+  for (int i = 0; i < m; ++i) {
+    const int n = (int)((i + 1 < m ? tab[i + 1].tile0 : tiles) - tab[i].tile0);
+    const float* si = sc.data() + tab[i].tile0;
+    idx.resize(n);
+    for (int k = 0; k < n; ++k) idx[k] = k;
+    std::stable_sort(idx.begin(), idx.end(), [&](int32_t x, int32_t y) { return si[x] > si[y]; });
+    for (int k = 0; k < n_top[i]; ++k) tile_ids[at + k] = idx[k];
+    at += n_top[i];
+  }
   return FH_OK;
 }

@@ -89,6 +89,8 @@ SIGNATURES = {
                                    C.c_void_p]),
     "fh_batch_select": (C.c_int, [C.c_void_p, C.POINTER(SelectOpts), C.POINTER(Candidate), C.c_int32,
                                   C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_void_p]),
+    "fh_batch_propose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_void_p,
+                                   C.c_void_p]),
     "fh_select": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SelectOpts), C.c_void_p, C.c_int32,
                             C.POINTER(C.c_int32), C.c_void_p]),
     "fh_cnn_create": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p)]),
@@ -487,6 +489,24 @@ def fh_tiles(hmap, origins, stream=None):
     _check(lib().fh_tiles(C.c_void_p(_ptr(hmap)), n_k, n_x0, C.c_void_p(_ptr(origins)), n, C.c_void_p(_ptr(tiles)),
                           C.c_void_p(_ptr(mean)), C.c_void_p(_ptr(istd)), _stream(stream)), "fh_tiles")
     return tiles
+
+
+def fh_batch_propose(net: CNN, batch: Batch, n_top: Sequence[int], stream=None):
+    """(scores CUDA float32 [all tiles, map after map], list of each map's best
+    tile indices)."""
+    import torch
+    plans = batch._keep[0]
+    n_tiles = [((p.n_k + 63) // 64) * ((p.n_x0 + 63) // 64) for p in plans]
+    scores = torch.empty(max(1, sum(n_tiles)), dtype=torch.float32, device=batch._keep[2][0].device)
+    nt = (C.c_int32 * len(plans))(*[int(x) for x in n_top])
+    ids = np.zeros(max(1, sum(int(x) for x in n_top)), dtype=np.int32)
+    _check(lib().fh_batch_propose(net.handle, batch.handle, C.c_void_p(_ptr(scores)), nt, ids.ctypes.data,
+                                  _stream(stream)), "fh_batch_propose")
+    out, at = [], 0
+    for x in n_top:
+        out.append([int(i) for i in ids[at:at + int(x)]])
+        at += int(x)
+    return scores[:sum(n_tiles)], out
 
 
 def fh_propose(net: CNN, plan: Plan, hmap, n_top: int, stream=None):

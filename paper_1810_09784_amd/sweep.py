@@ -144,12 +144,14 @@ def evaluate(sw: Sweep, net=None, sq=(8, 8), top_frac: float = 0.1, thresholds=(
     n_tiles = 0
     if net is not None:
         t0 = time.perf_counter()
-        props = []
+        tops, tbs = [], []
         for m in sw.maps:
             ta, tb = (m["plan"].n_k + 63) // 64, (m["plan"].n_x0 + 63) // 64
-            n_top = max(1, int(math.ceil(top_frac * ta * tb)))
+            tops.append(max(1, int(math.ceil(top_frac * ta * tb))))
+            tbs.append(tb)
             n_tiles += ta * tb
-            props.append((set(fh.fh_propose(net, m["plan"], m["hmap"], n_top)[1]), tb))
+        _, best = fh.fh_batch_propose(net, sw.batch, tops)  # every map's tiles through the network at once
+        props = [(set(b), tb) for b, tb in zip(best, tbs)]
         t_prop = time.perf_counter() - t0
     # injections' true cells, per map
     truth: Dict[int, List] = {}

@@ -74,3 +74,24 @@ def test_batch_select_rejects_options_invalid_for_a_map(batch48):
         batch.select(n_k_min + 1, 1)
     with pytest.raises(fh.FHError):
         batch.select(1, 257)
+
+
+def test_batch_propose_equals_per_map(batch48):
+    # the tiles of all 48 maps through one network, mixed in its batches:
+    # every score and every map's top tiles as fh_propose gives them map by map
+    import torch
+    from paper_1810_09784_amd import fh
+    specs, pms, plans, maps, batch = batch48
+    net = fh.CNN(max_batch=64)
+    rng = np.random.default_rng(4)
+    net.set_params(rng.normal(0.0, 0.08, net.n_params).astype(np.float32))
+    n_tiles = [((p.n_k + 63) // 64) * ((p.n_x0 + 63) // 64) for p in plans]
+    tops = [min(t, 1 + i % 3) for i, t in enumerate(n_tiles)]
+    scores, best = fh.fh_batch_propose(net, batch, tops)
+    at = 0
+    for pl, H, t, k, b in zip(plans, maps, n_tiles, tops, best):
+        s1, ids = fh.fh_propose(net, pl, H, k)
+        assert torch.equal(scores[at:at + t], s1)
+        assert ids == b
+        at += t
+    assert at == scores.numel()
