@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+BF16_PEAK_TFLOPS = 2500.0  # dense matrix cores
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_k_queue_large_map.md")
 KERNEL_SOURCES = ("paper_1810_09784_amd/csrc/fh_hough.hip", "paper_1810_09784_amd/csrc/fh_plan.cpp",
                   "paper_1810_09784_amd/csrc/fh_internal.h")
@@ -174,6 +175,36 @@ def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_
     log(f"layout: paper grid {ms_g:.3f} ms ({len(ks)} rows), coincide {ms_c:.3f} ms ({len(pts)} points), "
         f"project {ms_proj:.3f} ms, ROI refine {s_roi:.2f} s")
     return sweep_out, layout
+
+
+def run_cnn(fh, dev, stream, B=256, reps=20):
+    """Forward passes and training steps of the tile CNN on B random tiles:
+    throughput against the BF16 dense matrix-core peak (about 492 MFLOP per
+    tile forward, 3x that per training tile)."""
+    import numpy as np
+    import torch
+    net = fh.CNN(max_batch=B)
+    rng = np.random.default_rng(1)
+    net.set_params(rng.normal(0.0, 0.05, net.n_params).astype(np.float32))
+    x = torch.from_numpy(rng.normal(0.0, 1.0, (B, 64, 64)).astype(np.float32)).to(dev).to(torch.bfloat16)
+    lab = torch.from_numpy((rng.random(B) < 0.5).astype(np.float32)).to(dev)
+    fwd = timed(lambda: net.forward(x, stream=stream), reps, 3, stream)
+
+    def train():
+        net.forward(x, stream=stream)
+        net.backward(lab, stream=stream)
+        net.step(1e-3, stream=stream)
+
+    trn = timed(train, reps // 2, 2, stream)
+    net.destroy()
+    f_fwd = 492.0e6 * B
+    tf_fwd, tf_trn = f_fwd / (fwd * 1e-3) / 1e12, 3 * f_fwd / (trn * 1e-3) / 1e12
+    log(f"cnn: forward {fwd:.3f} ms / {B} tiles ({tf_fwd:.0f} TFLOP/s), training step {trn:.3f} ms "
+        f"({tf_trn:.0f} TFLOP/s)")
+    return {"tiles_per_batch": B, "forward_ms": round(fwd, 4), "forward_tiles_per_s": B / (fwd * 1e-3),
+            "forward_tflops": round(tf_fwd, 1), "train_step_ms": round(trn, 4), "train_tflops": round(tf_trn, 1),
+            "peak_tflops": BF16_PEAK_TFLOPS, "forward_mfma_frac": round(tf_fwd / BF16_PEAK_TFLOPS, 4),
+            "train_mfma_frac": round(tf_trn / BF16_PEAK_TFLOPS, 4)}
 
 
 def timed_steps(step, K, W, stream):
@@ -365,6 +396,10 @@ def main():
                           "updates_per_s_batched": Ub / (ms_b * 1e-3), "updates_per_s_plain": Ub / (ms_p * 1e-3),
                           "speedup_vs_plain": round(ms_p / ms_b, 3)}
         batch.destroy()
+
+    # ------------------------------------ the tile CNN on the matrix cores --
+    if not a.no_sweep:
+        out["cnn"] = run_cnn(fh, dev, stream)
 
     # ------------------------------------------- the full sweep and extras --
     if not a.no_sweep:

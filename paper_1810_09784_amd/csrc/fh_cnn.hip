@@ -80,84 +80,102 @@ __device__ __forceinline__ f4 mfma(typename Frag<KW>::T a, typename Frag<KW>::T 
 }
 
 // ------------------------------------------------------------ conv (GEMM) --
-// Implicit-GEMM 3x3 convolution on the matrix cores.  One work-group = 4
-// output rows of one tile (a wavefront per row: 4 pixel tiles of 16 x all
-// output-channel tiles of 16).  Rows y0-1 .. y0+4 of the input (with the zero
-// border) and the whole weight matrix are staged in LDS.
+// Implicit-GEMM 3x3 convolution on the matrix cores.  One work-group = 16
+// output rows of one tile, in groups of kConvWaves rows (a wavefront per row:
+// 4 pixel tiles of 16 x all output-channel tiles of 16).  The whole weight
+// matrix is staged in LDS once per work-group, and for each group the input
+// rows y0-1 .. y0+kConvWaves (with the zero border), all with 16-byte loads.
 //   FWD:  out = bf16(relu(bias + conv(in, w)))
 //   BWD:  out = bf16(conv(in, w) * (mask > 0))   (in = dY, w = flipped w^T,
 //         mask = the forward input of the layer: the ReLU derivative)
+constexpr int kConvWaves = 8;       // output rows per group
+constexpr int kConvRowsPerWG = 16;  // output rows per work-group
+
 template <int CIN, int COUT, bool BWD>
-__global__ void __launch_bounds__(256) k_conv(const bf16_t* __restrict__ in, const bf16_t* __restrict__ w,
-                                              const float* __restrict__ bias, const bf16_t* __restrict__ mask,
-                                              bf16_t* __restrict__ out) {
+__global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restrict__ in, const bf16_t* __restrict__ w,
+                                                          const float* __restrict__ bias,
+                                                          const bf16_t* __restrict__ mask, bf16_t* __restrict__ out) {
+  static_assert(CIN % 8 == 0 && (COUT * 9 * CIN) % 8 == 0 && HW % kConvRowsPerWG == 0 &&
+                    kConvRowsPerWG % kConvWaves == 0, "conv layout");
   constexpr int K = 9 * CIN;
   constexpr int KW = (K % 32 == 0) ? 32 : 16;
   constexpr int NCT = COUT / 16;
-  constexpr int ROWS = 6, COLS = HW + 2;
+  constexpr int ROWS = kConvWaves + 2, COLS = HW + 2;
+  constexpr int NT = kConvWaves * 64;
+  constexpr int VPP = CIN / 8;  // 16-byte vectors per pixel
+  constexpr int PARTS = HW / kConvRowsPerWG;
   extern __shared__ __align__(16) unsigned char smem[];
   bf16_t* xin = reinterpret_cast<bf16_t*>(smem);  // [ROWS][COLS][CIN]
   bf16_t* wl = xin + ROWS * COLS * CIN;           // [COUT][K]
-  const int b = blockIdx.x / (HW / 4);
-  const int y0 = (blockIdx.x % (HW / 4)) * 4;
+  const int b = blockIdx.x / PARTS;
+  const int yb = (blockIdx.x % PARTS) * kConvRowsPerWG;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bf16_t* inb = in + (size_t)b * NPIX * CIN;
-  // stage input rows (zero outside the tile) and weights
-  for (int e = tid; e < ROWS * COLS * CIN; e += 256) {
-    const int c = e % CIN, col = (e / CIN) % COLS, row = e / (CIN * COLS);
-    const int y = y0 - 1 + row, x = col - 1;
-    xin[e] = (y >= 0 && y < HW && x >= 0 && x < HW) ? inb[((size_t)y * HW + x) * CIN + c] : (bf16_t)0;
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(w);
+    uint4* dst = reinterpret_cast<uint4*>(wl);
+    for (int e = tid; e < COUT * K / 8; e += NT) dst[e] = src[e];
   }
-  for (int e = tid; e < COUT * K; e += 256) wl[e] = w[e];
-  __syncthreads();
-  f4 acc[4][NCT];
-#pragma unroll
-  for (int pt = 0; pt < 4; ++pt)
-#pragma unroll
-    for (int ct = 0; ct < NCT; ++ct) acc[pt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+  const bf16_t* inb = in + (size_t)b * NPIX * CIN;
+  bf16_t* ob = out + (size_t)b * NPIX * COUT;
   const int g = lane >> 4, m = lane & 15;
   constexpr int EL = KW / 4;  // bf16 per lane per fragment
-  for (int kc = 0; kc < K; kc += KW) {
-    const int k = kc + g * EL;
-    const int tap = k / CIN, ci = k % CIN;
-    const int dy = tap / 3, dx = tap % 3;
-    typename Frag<KW>::T bf[NCT];
-#pragma unroll
-    for (int ct = 0; ct < NCT; ++ct)
-      bf[ct] = *reinterpret_cast<const typename Frag<KW>::T*>(wl + (ct * 16 + m) * K + k);
-#pragma unroll
-    for (int pt = 0; pt < 4; ++pt) {
-      const int x = pt * 16 + m;
-      const typename Frag<KW>::T af =
-          *reinterpret_cast<const typename Frag<KW>::T*>(xin + ((wave + dy) * COLS + (x + dx)) * CIN + ci);
-#pragma unroll
-      for (int ct = 0; ct < NCT; ++ct) acc[pt][ct] = mfma<KW>(af, bf[ct], acc[pt][ct]);
+  for (int y0 = yb; y0 < yb + kConvRowsPerWG; y0 += kConvWaves) {
+    __syncthreads();  // the previous group is done with xin
+    for (int e = tid; e < ROWS * COLS * VPP; e += NT) {
+      const int v = e % VPP, col = (e / VPP) % COLS, row = e / (VPP * COLS);
+      const int y = y0 - 1 + row, x = col - 1;
+      uint4 val = uint4{0u, 0u, 0u, 0u};
+      if (y >= 0 && y < HW && x >= 0 && x < HW)
+        val = reinterpret_cast<const uint4*>(inb + ((size_t)y * HW + x) * CIN)[v];
+      reinterpret_cast<uint4*>(xin)[e] = val;
     }
-  }
-  const int y = y0 + wave;
-  bf16_t* ob = out + (size_t)b * NPIX * COUT;
+    __syncthreads();
+    f4 acc[4][NCT];
 #pragma unroll
-  for (int pt = 0; pt < 4; ++pt)
+    for (int pt = 0; pt < 4; ++pt)
 #pragma unroll
-    for (int ct = 0; ct < NCT; ++ct)
+      for (int ct = 0; ct < NCT; ++ct) acc[pt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < K; kc += KW) {
+      const int k = kc + g * EL;
+      const int tap = k / CIN, ci = k % CIN;
+      const int dy = tap / 3, dx = tap % 3;
+      typename Frag<KW>::T bf[NCT];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int x = pt * 16 + g * 4 + i;
-        const int co = ct * 16 + m;
-        const size_t o = ((size_t)y * HW + x) * COUT + co;
-        float v = acc[pt][ct][i];
-        if (BWD) {
-          v = bf2f(mask[(size_t)b * NPIX * COUT + o]) > 0.f ? v : 0.f;
-        } else {
-          v = fmaxf(v + bias[co], 0.f);
-        }
-        ob[o] = f2bf(v);
+      for (int ct = 0; ct < NCT; ++ct)
+        bf[ct] = *reinterpret_cast<const typename Frag<KW>::T*>(wl + (ct * 16 + m) * K + k);
+#pragma unroll
+      for (int pt = 0; pt < 4; ++pt) {
+        const int x = pt * 16 + m;
+        const typename Frag<KW>::T af =
+            *reinterpret_cast<const typename Frag<KW>::T*>(xin + ((wave + dy) * COLS + (x + dx)) * CIN + ci);
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) acc[pt][ct] = mfma<KW>(af, bf[ct], acc[pt][ct]);
       }
+    }
+    const int y = y0 + wave;
+#pragma unroll
+    for (int pt = 0; pt < 4; ++pt)
+#pragma unroll
+      for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int x = pt * 16 + g * 4 + i;
+          const int co = ct * 16 + m;
+          const size_t o = ((size_t)y * HW + x) * COUT + co;
+          float v = acc[pt][ct][i];
+          if (BWD) {
+            v = bf2f(mask[(size_t)b * NPIX * COUT + o]) > 0.f ? v : 0.f;
+          } else {
+            v = fmaxf(v + bias[co], 0.f);
+          }
+          ob[o] = f2bf(v);
+        }
+  }
 }
 
 template <int CIN, int COUT>
 constexpr int conv_lds() {
-  return (6 * (HW + 2) * CIN + COUT * 9 * CIN) * 2;
+  return ((kConvWaves + 2) * (HW + 2) * CIN + COUT * 9 * CIN) * 2;
 }
 
 // Weight gradient of a 3x3 convolution on the matrix cores: dW[co][k] +=
@@ -548,7 +566,9 @@ fh_status launch_conv(const bf16_t* in, const bf16_t* w, const float* bias, cons
                       hipStream_t s) {
   constexpr int lds = conv_lds<CIN, COUT>();
   (void)hipFuncSetAttribute((const void*)k_conv<CIN, COUT, BWD>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  hipLaunchKernelGGL((k_conv<CIN, COUT, BWD>), dim3(B * (HW / 4)), dim3(256), lds, s, in, w, bias, mask, out);
+  static_assert(lds <= 160 * 1024, "conv LDS");
+  hipLaunchKernelGGL((k_conv<CIN, COUT, BWD>), dim3(B * (HW / kConvRowsPerWG)), dim3(kConvWaves * 64), lds, s, in, w,
+                     bias, mask, out);
   return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
 }
 
