@@ -137,7 +137,7 @@ def evaluate(sw: Sweep, net=None, sq=(8, 8), top_frac: float = 0.1, thresholds=(
     sw.batch.launch()  # the maps of this evaluation
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    cands = sw.batch.select(sq[0], sq[1], 3)  # every map in one batched pass
+    cands = sw.batch.select(sq[0], sq[1], 3, as_dicts=False)  # every map in one batched pass
     t_sel = time.perf_counter() - t0
     props = None
     t_prop = 0.0
