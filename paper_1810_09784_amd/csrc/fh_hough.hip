@@ -556,23 +556,33 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
 // back from the map: grid (split tiles, kSelSplitParts), each work-group
 // takes a run of the tile's columns, cut into kSelSplitWaves pieces, and its
 // waves take the (row, piece) pairs.
-constexpr int kSelSplitParts = 16;
+constexpr int kSelSplitParts = 4;
 constexpr int kSelSplitWaves = 4;
+
+constexpr int kSelSplitUnroll = 4;  // steps whose loads are in flight together
 
 __device__ void sel_chunks(const MapArgs& M, const GMap& G, int r, int c0, int W, int k0, int k1, int lane) {
   SelRun sr(M, r, lane);
   const gptr<const int> row = (gptr<const int>)G.map + (size_t)r * M.n_x0 + c0;
-  for (int kb = k0; kb < k1; kb += kWave) {
-    const int k = kb + lane;
-    const int c = 4 * k;
-    v4i v = v4i{0, 0, 0, 0};
-    if (k < k1) {
-      if (c < W) v.x = row[c];
-      if (c + 1 < W) v.y = row[c + 1];
-      if (c + 2 < W) v.z = row[c + 2];
-      if (c + 3 < W) v.w = row[c + 3];
+  for (int kb = k0; kb < k1; kb += kSelSplitUnroll * kWave) {
+    v4i v[kSelSplitUnroll];
+#pragma unroll
+    for (int u = 0; u < kSelSplitUnroll; ++u) {
+      const int k = kb + u * kWave + lane;
+      const int c = 4 * k;
+      v[u] = v4i{0, 0, 0, 0};
+      if (k < k1) {
+        if (c < W) v[u].x = row[c];
+        if (c + 1 < W) v[u].y = row[c + 1];
+        if (c + 2 < W) v[u].z = row[c + 2];
+        if (c + 3 < W) v[u].w = row[c + 3];
+      }
     }
-    sr.step(v, c0 + c, c0 + 4 * kb, c0 + min(4 * min(kb + kWave, k1), W));
+#pragma unroll
+    for (int u = 0; u < kSelSplitUnroll; ++u) {
+      const int ks = kb + u * kWave;
+      if (ks < k1) sr.step(v[u], c0 + 4 * (ks + lane), c0 + 4 * ks, c0 + min(4 * min(ks + kWave, k1), W));
+    }
   }
   sr.flush();
 }
