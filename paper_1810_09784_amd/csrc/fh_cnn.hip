@@ -187,6 +187,7 @@ constexpr int conv_lds() {
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ in, const bf16_t* __restrict__ dy,
                                                     float* __restrict__ dw, float* __restrict__ db) {
+  static_assert(CIN % 8 == 0 && COUT % 8 == 0, "16-byte staging of 8 channels");
   constexpr int K = 9 * CIN;
   constexpr int MT = COUT / 16, NT = K / 16, TILES = MT * NT;
   constexpr int TPW = (TILES + 3) / 4;  // tiles per wavefront
@@ -201,23 +202,53 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
   f4 acc[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
-  float bsum = 0.f;  // dbias partial: thread tid < COUT
+  float bsum = 0.f;  // dbias partial: threads 4 co .. 4 co + 3 hold channel co, 16 pixels each
   for (int y = 0; y < HW; ++y) {
     __syncthreads();
-    for (int e = tid; e < COUT * HW; e += 256) {
-      const int co = e % COUT, x = e / COUT;
-      dyT[co * HW + x] = dyb[((size_t)y * HW + x) * COUT + co];
+    // dY row y transposed: one 16-byte load (8 channels of a pixel), 8 LDS stores
+    for (int e = tid; e < HW * (COUT / 8); e += 256) {
+      const int x = e / (COUT / 8), c8 = (e % (COUT / 8)) * 8;
+      const uint4 v = *reinterpret_cast<const uint4*>(dyb + ((size_t)y * HW + x) * COUT + c8);
+      const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        dyT[(c8 + 2 * i) * HW + x] = (bf16_t)(w[i] & 0xffffu);
+        dyT[(c8 + 2 * i + 1) * HW + x] = (bf16_t)(w[i] >> 16);
+      }
     }
-    for (int e = tid; e < 9 * CIN * HW; e += 256) {
-      const int ci = e % CIN, x = (e / CIN) % HW, t = e / (CIN * HW);
-      const int ddx = t % 3, ddy = t / 3;
-      const int yy = y + ddy - 1, xx = x + ddx - 1;
-      xT[((ddx * 3 + ddy) * CIN + ci) * HW + x] =
-          (yy >= 0 && yy < HW && xx >= 0 && xx < HW) ? inb[((size_t)yy * HW + xx) * CIN + ci] : (bf16_t)0;
+    // input rows y-1 .. y+1, each pixel loaded once (8 channels, zero outside the
+    // tile) and stored into the dx-shifted copies it feeds: copy ddx holds
+    // X[yy][x + ddx - 1] at column x
+    for (int e = tid; e < 3 * (HW + 2) * (CIN / 8); e += 256) {
+      const int c8 = (e % (CIN / 8)) * 8, xx = (e / (CIN / 8)) % (HW + 2) - 1, ddy = e / ((CIN / 8) * (HW + 2));
+      const int yy = y + ddy - 1;
+      uint4 v = uint4{0u, 0u, 0u, 0u};
+      if (yy >= 0 && yy < HW && xx >= 0 && xx < HW)
+        v = *reinterpret_cast<const uint4*>(inb + ((size_t)yy * HW + xx) * CIN + c8);
+      const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int ddx = 0; ddx < 3; ++ddx) {
+        const int x = xx - ddx + 1;
+        if (x < 0 || x >= HW) continue;
+        bf16_t* dst = xT + ((ddx * 3 + ddy) * CIN + c8) * HW + x;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          dst[(2 * i) * HW] = (bf16_t)(w[i] & 0xffffu);
+          dst[(2 * i + 1) * HW] = (bf16_t)(w[i] >> 16);
+        }
+      }
     }
     __syncthreads();
-    if (tid < COUT)
-      for (int x = 0; x < HW; ++x) bsum += bf2f(dyT[tid * HW + x]);
+    if (tid < 4 * COUT) {
+      const uint4* src = reinterpret_cast<const uint4*>(dyT + (tid >> 2) * HW + (tid & 3) * 16);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint4 v = src[h];
+        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) bsum += __uint_as_float(w[i] << 16) + __uint_as_float(w[i] & 0xffff0000u);
+      }
+    }
     for (int pc = 0; pc < HW; pc += 32) {  // 32 pixels per MFMA step
       const int x = pc + g * 8;
 #pragma unroll
@@ -249,7 +280,9 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
       }
     }
   }
-  if (tid < COUT) atomicAdd(&db[tid], bsum);
+  bsum += __shfl_xor(bsum, 1);
+  bsum += __shfl_xor(bsum, 2);
+  if (tid < 4 * COUT && (tid & 3) == 0) atomicAdd(&db[tid >> 2], bsum);
 }
 
 template <int CIN, int COUT>
