@@ -393,7 +393,12 @@ __global__ void __launch_bounds__(kHeadThreads) k_head_fwd(const bf16_t* __restr
 }
 
 // Binary cross-entropy of the batch (mean) and its gradient back to act4.
-__global__ void __launch_bounds__(256) k_head_bwd(const bf16_t* __restrict__ act4, const float* __restrict__ feat,
+// One work-group per tile; the gradient to act4 (w5 dz / NPIX where act4 > 0)
+// goes out 8 channels (16 bytes) per thread and step.
+constexpr int kHeadBwdThreads = 1024;
+
+__global__ void __launch_bounds__(kHeadBwdThreads) k_head_bwd(const bf16_t* __restrict__ act4,
+                                                              const float* __restrict__ feat,
                                                   const float* __restrict__ logit, const float* __restrict__ label,
                                                   const float* __restrict__ w5, float* __restrict__ dw5,
                                                   float* __restrict__ db5, float* __restrict__ loss,
@@ -409,11 +414,21 @@ __global__ void __launch_bounds__(256) k_head_bwd(const bf16_t* __restrict__ act
     const float l = fmaxf(z, 0.f) - z * yv + log1pf(expf(-fabsf(z)));
     atomicAdd(loss, l / (float)B);
   }
-  for (int e = threadIdx.x; e < NPIX * C4; e += 256) {
-    const int c = e % C4;
-    const size_t o = (size_t)b * NPIX * C4 + e;
-    const float g = bf2f(act4[o]) > 0.f ? dz * w5[c] * (1.0f / NPIX) : 0.f;
-    dact4[o] = f2bf(g);
+  static_assert(C4 % 8 == 0, "8 channels per 16 bytes");
+  const uint4* a = reinterpret_cast<const uint4*>(act4 + (size_t)b * NPIX * C4);
+  uint4* d = reinterpret_cast<uint4*>(dact4 + (size_t)b * NPIX * C4);
+  for (int e = threadIdx.x; e < NPIX * C4 / 8; e += kHeadBwdThreads) {
+    const int c = (e % (C4 / 8)) * 8;
+    const uint4 v = a[e];
+    const unsigned w[4] = {v.x, v.y, v.z, v.w};
+    unsigned o[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float g0 = __uint_as_float(w[i] << 16) > 0.f ? dz * w5[c + 2 * i] * (1.0f / NPIX) : 0.f;
+      const float g1 = __uint_as_float(w[i] & 0xffff0000u) > 0.f ? dz * w5[c + 2 * i + 1] * (1.0f / NPIX) : 0.f;
+      o[i] = (unsigned)f2bf(g0) | ((unsigned)f2bf(g1) << 16);
+    }
+    d[e] = uint4{o[0], o[1], o[2], o[3]};
   }
 }
 
@@ -708,7 +723,7 @@ extern "C" fh_status fh_cnn_backward(fh_cnn_t h, const float* labels, int32_t B,
   hipStream_t s = (hipStream_t)stream;
   if (hipMemsetAsync(c->grads, 0, NPARAM * 4, s) != hipSuccess || hipMemsetAsync(c->loss, 0, 4, s) != hipSuccess)
     return FH_EDEVICE;
-  hipLaunchKernelGGL(k_head_bwd, dim3(B), dim3(256), 0, s, c->a4, c->feat, c->logit, labels, c->params + OFF_W5,
+  hipLaunchKernelGGL(k_head_bwd, dim3(B), dim3(kHeadBwdThreads), 0, s, c->a4, c->feat, c->logit, labels, c->params + OFF_W5,
                      c->grads + OFF_W5, c->grads + OFF_B5, c->loss, c->d4, B);
   fh_status st = launch_wgrad<C3, C4>(c->a3, c->d4, c->grads + OFF_W4, c->grads + OFF_B4, B, s);
   if (st == FH_OK) st = launch_conv<C4, C3, true>(c->d4, c->w4t, nullptr, c->a3, c->d3, B, s);
