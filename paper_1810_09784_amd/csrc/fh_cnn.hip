@@ -205,36 +205,47 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
   float bsum = 0.f;  // dbias partial: threads 4 co .. 4 co + 3 hold channel co, 16 pixels each
   for (int y = 0; y < HW; ++y) {
     __syncthreads();
-    // dY row y transposed: one 16-byte load (8 channels of a pixel), 8 LDS stores
-    for (int e = tid; e < HW * (COUT / 8); e += 256) {
-      const int x = e / (COUT / 8), c8 = (e % (COUT / 8)) * 8;
-      const uint4 v = *reinterpret_cast<const uint4*>(dyb + ((size_t)y * HW + x) * COUT + c8);
-      const unsigned w[4] = {v.x, v.y, v.z, v.w};
+    // dY row y transposed.  A thread takes two adjacent pixels x, x+1 (x even)
+    // and 8 channels: two 16-byte loads, 8 stores of the (x, x+1) pair as one
+    // aligned 32-bit word.
+    for (int e = tid; e < (HW / 2) * (COUT / 8); e += 256) {
+      const int x = (e / (COUT / 8)) * 2, c8 = (e % (COUT / 8)) * 8;
+      const uint4 v0 = *reinterpret_cast<const uint4*>(dyb + ((size_t)y * HW + x) * COUT + c8);
+      const uint4 v1 = *reinterpret_cast<const uint4*>(dyb + ((size_t)y * HW + x + 1) * COUT + c8);
+      const unsigned a[4] = {v0.x, v0.y, v0.z, v0.w}, b[4] = {v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        dyT[(c8 + 2 * i) * HW + x] = (bf16_t)(w[i] & 0xffffu);
-        dyT[(c8 + 2 * i + 1) * HW + x] = (bf16_t)(w[i] >> 16);
+        *reinterpret_cast<unsigned*>(dyT + (c8 + 2 * i) * HW + x) = (a[i] & 0xffffu) | (b[i] << 16);
+        *reinterpret_cast<unsigned*>(dyT + (c8 + 2 * i + 1) * HW + x) = (a[i] >> 16) | (b[i] & 0xffff0000u);
       }
     }
-    // input rows y-1 .. y+1, each pixel loaded once (8 channels, zero outside the
-    // tile) and stored into the dx-shifted copies it feeds: copy ddx holds
-    // X[yy][x + ddx - 1] at column x
-    for (int e = tid; e < 3 * (HW + 2) * (CIN / 8); e += 256) {
-      const int c8 = (e % (CIN / 8)) * 8, xx = (e / (CIN / 8)) % (HW + 2) - 1, ddy = e / ((CIN / 8) * (HW + 2));
+    // input rows y-1 .. y+1 as three dx-shifted transposed copies: copy ddx holds
+    // X[yy][x + ddx - 1] at column x (zero outside the tile).  A thread takes a
+    // column pair (x, x+1), x even, and 8 channels: it loads the pixels x-1 ..
+    // x+2 once and stores the pair of every copy as one aligned 32-bit word.
+    for (int e = tid; e < 3 * (HW / 2) * (CIN / 8); e += 256) {
+      const int c8 = (e % (CIN / 8)) * 8, x = ((e / (CIN / 8)) % (HW / 2)) * 2, ddy = e / ((CIN / 8) * (HW / 2));
       const int yy = y + ddy - 1;
-      uint4 v = uint4{0u, 0u, 0u, 0u};
-      if (yy >= 0 && yy < HW && xx >= 0 && xx < HW)
-        v = *reinterpret_cast<const uint4*>(inb + ((size_t)yy * HW + xx) * CIN + c8);
-      const unsigned w[4] = {v.x, v.y, v.z, v.w};
+      unsigned px[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int xx = x - 1 + q;
+        uint4 v = uint4{0u, 0u, 0u, 0u};
+        if (yy >= 0 && yy < HW && xx >= 0 && xx < HW)
+          v = *reinterpret_cast<const uint4*>(inb + ((size_t)yy * HW + xx) * CIN + c8);
+        px[q][0] = v.x;
+        px[q][1] = v.y;
+        px[q][2] = v.z;
+        px[q][3] = v.w;
+      }
 #pragma unroll
       for (int ddx = 0; ddx < 3; ++ddx) {
-        const int x = xx - ddx + 1;
-        if (x < 0 || x >= HW) continue;
         bf16_t* dst = xT + ((ddx * 3 + ddy) * CIN + c8) * HW + x;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          dst[(2 * i) * HW] = (bf16_t)(w[i] & 0xffffu);
-          dst[(2 * i + 1) * HW] = (bf16_t)(w[i] >> 16);
+          const unsigned lo = px[ddx][i], hi = px[ddx + 1][i];  // pixels x + ddx - 1 and x + ddx
+          *reinterpret_cast<unsigned*>(dst + (2 * i) * HW) = (lo & 0xffffu) | (hi << 16);
+          *reinterpret_cast<unsigned*>(dst + (2 * i + 1) * HW) = (lo >> 16) | (hi & 0xffff0000u);
         }
       }
     }
