@@ -312,11 +312,18 @@ __global__ void __launch_bounds__(256) k_conv1_fwd(const bf16_t* __restrict__ in
     const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
     v[tap] = (yy >= 0 && yy < HW && xx >= 0 && xx < HW) ? bf2f(in[(size_t)b * NPIX + yy * HW + xx]) : 0.f;
   }
+  static_assert(C1 % 8 == 0, "16-byte stores of 8 channels");
+  unsigned pk[C1 / 2];  // the pixel's C1 channels, packed in pairs
+#pragma unroll
   for (int co = 0; co < C1; ++co) {
     float s = 0.f;
     for (int tap = 0; tap < 9; ++tap) s += bf2f(f2bf(w1[co * 9 + tap])) * v[tap];
-    out[(size_t)t * C1 + co] = f2bf(fmaxf(s + b1[co], 0.f));
+    const unsigned h = f2bf(fmaxf(s + b1[co], 0.f));
+    pk[co / 2] = (co & 1) ? (pk[co / 2] | (h << 16)) : h;
   }
+  uint4* o = reinterpret_cast<uint4*>(out + (size_t)t * C1);
+#pragma unroll
+  for (int q = 0; q < C1 / 8; ++q) o[q] = uint4{pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]};
 }
 
 // dW1[co][tap] = sum_p dY1[p][co] * in[p + tap]; one work-group per tile.
