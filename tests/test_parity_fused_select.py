@@ -107,7 +107,8 @@ def test_fused_large_map(dev, oracle):
     from oracle import select as OS
     spec = S.cfg_single_large()
     pm = S.make_peakmap(spec)
-    plan = fh.Plan.from_spec(spec)
+    from paper_1810_09784_amd import tune
+    plan = fh.Plan.from_spec(spec, tile=tune.lookup(spec, pm.n_peaks))  # the benchmark's launch configuration
     d = oracle.Desc.from_spec(spec)
     ref_map = oracle.hough(d, pm.row_ptr, pm.bin)
     got_map, got, n = _fused(plan, pm, dev, (5, 5))
