@@ -799,11 +799,20 @@ __device__ __forceinline__ int prep_group(int n_words) {
   return F;
 }
 
-__device__ void prepare_fft_lds(const MapArgs& M, int i, int lane, unsigned* cnt, unsigned* msk,
-                                unsigned long long* rbuf, int pitch) {
+// The first kPrepUnroll * 64 bins of peaks [lo, hi), one per lane and step.
+__device__ __forceinline__ void prep_bins(const GMap& G, int lo, int hi, int lane, int* jv) {
+#pragma unroll
+  for (int u = 0; u < kPrepUnroll; ++u) {
+    const int p = lo + u * kWave + lane;
+    jv[u] = p < hi ? G.bin[p] : 0;
+  }
+}
+
+// One FFT (peaks [lo, hi)) into the wave's LDS counts and masks, then its
+// rank words into rbuf; j0 holds its first step of bins, loaded beforehand.
+__device__ void prepare_fft_lds(const MapArgs& M, int lo, int hi, const int* j0, int lane, unsigned* cnt,
+                                unsigned* msk, unsigned long long* rbuf, int pitch) {
   const GMap G(M);
-  const int lo = min(max(G.row_ptr[i], 0), M.n_peaks);
-  const int hi = min(max(G.row_ptr[i + 1], lo), M.n_peaks);
   for (int w = lane; w < M.n_words; w += kWave) {
     cnt[w] = 0;
     msk[w] = 0;
@@ -813,10 +822,11 @@ __device__ void prepare_fft_lds(const MapArgs& M, int i, int lane, unsigned* cnt
   int last = INT_MIN;  // bin of the previous peak of this FFT
   for (int p0 = lo; p0 < hi; p0 += kPrepUnroll * kWave) {
     int jv[kPrepUnroll];  // all loads of the step in flight before the first use
+    if (p0 == lo) {
 #pragma unroll
-    for (int u = 0; u < kPrepUnroll; ++u) {
-      const int p = p0 + u * kWave + lane;
-      jv[u] = p < hi ? G.bin[p] : 0;
+      for (int u = 0; u < kPrepUnroll; ++u) jv[u] = j0[u];
+    } else {
+      prep_bins(G, p0, hi, lane, jv);
     }
 #pragma unroll
     for (int u = 0; u < kPrepUnroll; ++u) {
@@ -898,8 +908,23 @@ __device__ void prepare_map(const MapArgs& M, unsigned* lds) {
     for (int g = blockIdx.x; g < n_groups; g += gridDim.x) {
       const int i0 = g * F;
       const int nf = min(F, M.n_fft - i0);
-      for (int f = wave; f < nf; f += kPrepWaves)
-        prepare_fft_lds(M, uniform(i0 + f), lane, cnt, cnt + M.n_words, rbuf + f, pitch);
+      // the wave's FFTs in pairs: both CSR ranges, then both first steps of
+      // bins are in flight before the first FFT is processed
+      const GMap G(M);
+      for (int f = wave; f < nf; f += 2 * kPrepWaves) {
+        const int fb = f + kPrepWaves;
+        const bool two = fb < nf;  // uniform over the wavefront
+        const int ia = uniform(i0 + f), ibb = uniform(i0 + (two ? fb : f));
+        const int loA = min(max(G.row_ptr[ia], 0), M.n_peaks);
+        const int hiA = min(max(G.row_ptr[ia + 1], loA), M.n_peaks);
+        const int loB = min(max(G.row_ptr[ibb], 0), M.n_peaks);
+        const int hiB = min(max(G.row_ptr[ibb + 1], loB), M.n_peaks);
+        int jA[kPrepUnroll], jB[kPrepUnroll];
+        prep_bins(G, loA, hiA, lane, jA);
+        if (two) prep_bins(G, loB, hiB, lane, jB);
+        prepare_fft_lds(M, loA, hiA, jA, lane, cnt, cnt + M.n_words, rbuf + f, pitch);
+        if (two) prepare_fft_lds(M, loB, hiB, jB, lane, cnt, cnt + M.n_words, rbuf + fb, pitch);
+      }
       __syncthreads();
       const int n = M.n_words * F;
       for (int e = threadIdx.x; e < n; e += blockDim.x) {
