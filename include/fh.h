@@ -185,11 +185,12 @@ fh_status fh_select(fh_plan_t plan, const int32_t* map, const fh_select_opts* op
  * in the two rows each square picks.  Asynchronous on
  * `stream`: the square results are copied to pinned host memory owned by the
  * plan and an event is recorded; fetch them with fh_select_results.  A new
- * fh_hough_select (or an fh_select) of the same plan first waits for a
- * pending one, whose results are then dropped if they were not fetched; the
- * plan's scratch is shared, so one plan serves one such call at a time (use
- * two plans of the same map description to overlap steps).  Errors: those of
- * fh_hough and fh_select, FH_ENOMEM for the pinned buffer. */
+ * fh_hough_select of the same plan first waits for a pending one and drops
+ * its results if they were not fetched; an fh_select of the plan also waits
+ * for it (those results stay available).  The plan's scratch is shared, so
+ * one plan serves one such call at a time (use two plans of the same map
+ * description to overlap steps).  Errors: those of fh_hough and fh_select,
+ * FH_ENOMEM for the pinned buffer. */
 fh_status fh_hough_select(fh_plan_t plan, const fh_peaks* peaks, int32_t* map, const fh_select_opts* opts,
                           void* stream);
 
