@@ -221,3 +221,31 @@ def test_fused_one_column_segments(dev, oracle, cols):
     ref = OS.select(ref_map, spec.k, x0m, dx, spec.n, 3, hi - lo, 2, -1e300, lo, hi)
     assert n == len(ref)
     _compare(got, ref)
+
+
+def test_fused_pending_results_and_plain_select(dev, oracle):
+    # a plain fh_select on the same plan while fused results are pending leaves
+    # them fetchable; a second fused call drops unfetched results of the first
+    import torch
+    from paper_1810_09784_amd import fh
+    from oracle import select as OS
+    specs = [S.cfg_single_small(seed=s) for s in (21, 22)]
+    plan = fh.Plan.from_spec(specs[0])
+    d = oracle.Desc.from_spec(specs[0])
+    nf, x0m, dx, nx = oracle.grid(d)
+    pms = [S.make_peakmap(sp) for sp in specs]
+    dev_pk = [(torch.from_numpy(p.row_ptr).to(dev), torch.from_numpy(p.bin).to(dev)) for p in pms]
+    refs = [oracle.hough(d, p.row_ptr, p.bin) for p in pms]
+    H0 = torch.empty((plan.n_k, plan.n_x0), dtype=torch.int32, device=dev)
+    H1 = torch.from_numpy(refs[1]).to(dev)
+    fh.fh_hough_select(plan, *dev_pk[0], H0, 4, 4, 3)
+    plain, _ = fh.fh_select(plan, H1, 3, 5, 2)
+    _compare(plain, OS.select(refs[1], specs[0].k, x0m, dx, specs[0].n, 3, 5, 2))
+    got, _ = fh.fh_select_results(plan)
+    _compare(got, OS.select(refs[0], specs[0].k, x0m, dx, specs[0].n, 4, 4, 3))
+    fh.fh_hough_select(plan, *dev_pk[0], H0, 4, 4, 3)
+    fh.fh_hough_select(plan, *dev_pk[1], H0, 2, 6, 3)  # the first call's results are dropped
+    got, _ = fh.fh_select_results(plan)
+    _compare(got, OS.select(refs[1], specs[0].k, x0m, dx, specs[0].n, 2, 6, 3))
+    with pytest.raises(fh.FHError):
+        fh.fh_select_results(plan)
