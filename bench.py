@@ -131,6 +131,7 @@ def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_
                  "propose_s": round(ev["propose_s"], 3), "tiles_scored": ev["tiles"],
                  "efficiency": ev["curves"], "parity_sampled_rows": parity,
                  "note": "tile CNN trained on maps of this geometry drawn with other seeds (tile_cnn_sweep.npy)"}
+    sw_paper = run_sweep_paper_k(fh, dev, stream, K, check_oracle)
     # coincidences: the sweep's candidates against a second draw of the same maps'
     # candidates is not available, so the list is joined with itself moved by one bin
     cl = sw.batch.select(8, 8, 3)
@@ -174,6 +175,7 @@ def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_
               "roi_refine": {"candidates": len(roi), "cells_each": 60 * 60, "s_incl_plans": round(s_roi, 3)}}
     log(f"layout: paper grid {ms_g:.3f} ms ({len(ks)} rows), coincide {ms_c:.3f} ms ({len(pts)} points), "
         f"project {ms_proj:.3f} ms, ROI refine {s_roi:.2f} s")
+    layout["sweep_paper_k_grids"] = sw_paper
     return sweep_out, layout
 
 
@@ -205,6 +207,41 @@ def run_cnn(fh, dev, stream, B=256, reps=20):
             "forward_tflops": round(tf_fwd, 1), "train_step_ms": round(trn, 4), "train_tflops": round(tf_trn, 1),
             "peak_tflops": BF16_PEAK_TFLOPS, "forward_mfma_frac": round(tf_fwd / BF16_PEAK_TFLOPS, 4),
             "train_mfma_frac": round(tf_trn / BF16_PEAK_TFLOPS, 4)}
+
+
+def run_sweep_paper_k(fh, dev, stream, K, check_oracle):
+    """The sweep's 990 maps on the paper's k layout: each map on the geometric k
+    grid of Sec. VI.B over its T_FFT level's spindown range [1/(2 T_FFT)^2,
+    1/T_FFT^2] (Sec. VI.D) instead of 256 uniform rows."""
+    import numpy as np
+    from paper_1810_09784_amd import sweep
+    sw = sweep.Sweep(dev, log=log, k_layout="paper")
+    rows = [m["plan"].n_k for m in sw.maps]
+    ms_b = sweep.time_batch(sw, steps=K, warmup=1, stream=stream)
+    ev = sweep.evaluate(sw, None)
+    log(f"sweep (paper k grids): {sum(rows)} rows ({min(rows)}-{max(rows)} per map), batched {ms_b:.3f} ms, "
+        f"selection {ev['select_s']:.2f} s")
+    parity = None
+    if check_oracle:
+        from oracle import hough as oracle
+        parity = True
+        for mi in (0, len(sw.maps) // 2, len(sw.maps) - 1):
+            m = sw.maps[mi]
+            rpm, bnm = sw.peakmaps[(m["band"], m["ti"])]
+            r = [0, 1, m["plan"].n_k // 2, m["plan"].n_k - 1]
+            d = oracle.Desc(m["n"], m["tfft"], m["f_min"], m["f_max"], m["n_fft"], m["k"])
+            ref = oracle.hough(d, rpm.cpu().numpy(), bnm.cpu().numpy(), rows=r)
+            parity = parity and bool(np.array_equal(m["hmap"][r].cpu().numpy(), ref))
+        assert parity, "paper-grid sweep map differs from the oracle on sampled rows"
+    out = {"workload": "the 990 sweep maps, each on the geometric k grid of its T_FFT level "
+                       "(fdot 1/(2 T_FFT)^2 .. 1/T_FFT^2); 200 injections on grid rows",
+           "k_rows": int(sum(rows)), "rows_per_map": [int(min(rows)), int(max(rows))],
+           "updates_per_launch": sw.U, "ms_batched": round(ms_b, 4), "updates_per_s_batched": sw.U / (ms_b * 1e-3),
+           "select_s": round(ev["select_s"], 3), "efficiency_plain": [
+               {k: c[k] for k in ("cr_thr", "eff_plain", "noise_cands_plain")} for c in ev["curves"]],
+           "parity_sampled_rows": parity}
+    sw.destroy()
+    return out
 
 
 def timed_steps(step, K, W, stream):

@@ -9,6 +9,11 @@ sources, each drawn into one (band, T_FFT) peakmap with its n from the grid,
 f0 inside the band, k on one of the rows 2 .. n_k/2 - 1 of its map, and added
 power a uniform in [amp_lo, amp_hi].
 
+k_layout="paper" gives every map the geometric k grid of Sec. VI.B over the
+spindown range of its T_FFT level of Sec. VI.D, fdot in [1/(2 T_FFT)^2,
+1/T_FFT^2], instead of the uniform rows; injections then sit on rows of those
+grids.
+
 One run: all maps in one batched persistent launch (captured graph), the
 plain selection (sq_k x sq_x0 squares, second candidate 3 rows away) on
 every map in one batched pass, the tile CNN's scores of every 64 x 64 tile
@@ -25,6 +30,7 @@ from typing import Dict, List, Optional
 
 import numpy as np
 
+from . import grids as GR
 from . import synth as S
 
 N_VALUES = tuple(2.0 + 0.5 * i for i in range(11))
@@ -37,18 +43,29 @@ def band_edges(n_bands: int = 30, f_start: float = 100.0, width: float = 64.0):
     return [(f_start + width * b, f_start + width * (b + 1)) for b in range(n_bands)]
 
 
+def map_k(layout: str, n: float, tfft: float, lo: float, hi: float, n_k: int) -> np.ndarray:
+    """k rows of one map (ascending)."""
+    if layout == "uniform":
+        return S.uniform_k((1.0 / tfft ** 2) / lo ** n, n_k)
+    if layout == "paper":
+        return GR.k_grid(n, tfft, lo, hi, 1.0 / (2.0 * tfft) ** 2, 1.0 / tfft ** 2)[0]
+    raise ValueError("k_layout is 'uniform' or 'paper'")
+
+
 class Sweep:
     """Inputs, plans and maps of the sweep, resident on the GPU."""
 
     def __init__(self, dev, seed: int = 5, n_values=N_VALUES, tffts=TFFTS, n_bands: int = 30, t_obs: float = T_OBS,
-                 n_k: int = N_K, n_inj: int = 200, amp_lo: float = 1.0, amp_hi: float = 4.0, log=None):
+                 n_k: int = N_K, n_inj: int = 200, amp_lo: float = 1.0, amp_hi: float = 4.0, log=None,
+                 k_layout: str = "uniform"):
         import torch
         from . import fh
         self.dev = dev
         rng = np.random.default_rng(seed)
         self.bands = band_edges(n_bands)
         self.n_values, self.tffts = tuple(n_values), tuple(tffts)
-        # injections: (band, tfft index, n index, f0, k, amp)
+        self.k_layout = k_layout
+        # injections: (band, tfft index, n index, f0, k, amp, k row)
         inj = []
         for _ in range(n_inj):
             b = int(rng.integers(len(self.bands)))
@@ -56,12 +73,13 @@ class Sweep:
             ni = int(rng.integers(len(self.n_values)))
             lo, hi = self.bands[b]
             n = self.n_values[ni]
-            k_max = (1.0 / self.tffts[ti] ** 2) / lo ** n
-            # on a k row of its map: a uniform grid this coarse moves a track by many
-            # columns per row over days, so off-row sources smear over the map
-            k = float(S.uniform_k(k_max, n_k)[int(rng.integers(2, n_k // 2))])
+            # on a k row of its map: a grid this coarse moves a track by many columns
+            # per row over days, so off-row sources smear over the map
+            ks = map_k(k_layout, n, self.tffts[ti], lo, hi, n_k)
+            row = int(rng.integers(2, max(3, len(ks) // 2)))
+            k = float(ks[row])
             f0 = float(rng.uniform(lo + 4.0, hi - 4.0))
-            inj.append((b, ti, ni, f0, k, float(rng.uniform(amp_lo, amp_hi))))
+            inj.append((b, ti, ni, f0, k, float(rng.uniform(amp_lo, amp_hi)), row))
         self.injections = inj
         self.peakmaps = {}   # (band, ti) -> (row_ptr, bin)
         self.maps = []       # dicts: band, ti, ni, plan, hmap, peaks key, U
@@ -72,20 +90,19 @@ class Sweep:
                 n_fft = int(t_obs / tfft)
                 injs = [S.Injection(f0=f0, tau=1.0 / (k * (self.n_values[ni] - 1) * f0 ** (self.n_values[ni] - 1)),
                                     n=self.n_values[ni], amp=amp)
-                        for (bb, tt, ni, f0, k, amp) in inj if bb == b and tt == ti]
+                        for (bb, tt, ni, f0, k, amp, _) in inj if bb == b and tt == ti]
                 spec = S.MapSpec(f"b{b}t{tfft}", 3.0, tfft, lo, hi, n_fft, np.zeros(1), seed=seed * 100000 + b * 10 + ti,
                                  injections=injs)
                 rp, bn, _ = S.gpu_peakmap(spec, dev)
                 self.peakmaps[(b, ti)] = (rp, bn)
                 P = int(bn.numel())
                 for ni, n in enumerate(self.n_values):
-                    k_max = (1.0 / tfft ** 2) / lo ** n
-                    kk = S.uniform_k(k_max, n_k)
+                    kk = map_k(k_layout, n, tfft, lo, hi, n_k)
                     plan = fh.Plan(n, tfft, lo, hi, n_fft, kk)
                     hmap = torch.empty((plan.n_k, plan.n_x0), dtype=torch.int32, device=dev)
                     self.maps.append({"band": b, "ti": ti, "ni": ni, "n": n, "tfft": tfft, "f_min": lo, "f_max": hi,
                                       "n_fft": n_fft, "k": kk, "plan": plan, "hmap": hmap, "P": P})
-                    self.U += P * n_k
+                    self.U += P * len(kk)
         torch.cuda.synchronize()
         self.build_s = time.perf_counter() - t
         self.peaks_total = sum(int(bn.numel()) for _, bn in self.peakmaps.values())
@@ -155,12 +172,11 @@ def evaluate(sw: Sweep, net=None, sq=(8, 8), top_frac: float = 0.1, thresholds=(
         t_prop = time.perf_counter() - t0
     # injections' true cells, per map
     truth: Dict[int, List] = {}
-    for (b, ti, ni, f0, k, amp) in sw.injections:
+    for (b, ti, ni, f0, k, amp, row) in sw.injections:
         mi = sw.map_index(b, ti, ni)
         m = sw.maps[mi]
         info = m["plan"].info
         col = (f0 ** (1.0 - m["n"]) - info.x0_min) / info.dx0
-        row = k / (m["k"][1] - m["k"][0])
         truth.setdefault(mi, []).append((row, col))
     res = {"select_s": t_sel, "propose_s": t_prop, "tiles": n_tiles, "curves": []}
     noise_plain = {thr: 0 for thr in thresholds}
