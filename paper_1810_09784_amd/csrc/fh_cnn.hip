@@ -2,7 +2,7 @@
 // plain candidate selection's attention.  Not part of the paper's method: its
 // closing section only plans machine learning for the search; here a small
 // network is trained on maps the method itself produces from synthetic
-// injections, and the plain selection stays the judge.
+// injections, and the plain selection still decides.
 //
 // Network: tile (1 channel, counts normalised per map row) -> 4 x [conv 3x3,
 // stride 1, zero padding, bias, ReLU] with 1 -> 16 -> 32 -> 64 -> 64 channels
