@@ -33,6 +33,10 @@ def main():
     ap.add_argument("--geometry", default="small", choices=("small", "sweep"),
                     help="small: the n = 5, 500-600 Hz maps; sweep: the full sweep's maps")
     ap.add_argument("--sweep-maps", type=int, default=1250, help="training peakmaps of the sweep geometry")
+    ap.add_argument("--sweep-noise", type=int, default=5,
+                    help="noise-only sweeps that calibrate the fixed-FAP thresholds (0: none)")
+    ap.add_argument("--sweep-inj", type=int, default=200, help="injections of the evaluated sweep")
+    ap.add_argument("--sweep-faps", default="0.1,0.03,0.01", help="false-alarm probabilities per map on the sweep")
     a = ap.parse_args()
     import torch
     from . import fh, learn
@@ -76,8 +80,12 @@ def main():
     t = time.time()
     if a.geometry == "sweep":
         from . import sweep
-        sw = sweep.Sweep(dev, seed=a.seed + 100, log=log)
+        sw = sweep.Sweep(dev, seed=a.seed + 100, n_inj=a.sweep_inj, log=log)
         res["evaluation"] = sweep.evaluate(sw, net)
+        if a.sweep_noise > 0:
+            faps = [float(x) for x in a.sweep_faps.split(",")]
+            res["evaluation"]["at_fap"] = sweep.evaluate_at_fap(dev, net, faps, a.sweep_noise, a.seed + 100, sw=sw,
+                                                                log=log)
         sw.destroy()
     else:
         amps = [float(x) for x in a.amps.split(",")]

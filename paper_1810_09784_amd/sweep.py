@@ -209,6 +209,101 @@ def evaluate(sw: Sweep, net=None, sq=(8, 8), top_frac: float = 0.1, thresholds=(
     return res
 
 
+def _in_proposal(c, keep) -> bool:
+    return keep is None or (int(c["row"]) // 64) * keep[1] + (int(c["col"]) // 64) in keep[0]
+
+
+def _run_pipelines(sw: Sweep, net, sq, top_frac: float):
+    """Launch the batch, select on every map and, with a network, propose its
+    top tiles: (candidate records per map, (proposed tile set, tiles along x0)
+    per map or None)."""
+    import torch
+    from . import fh
+    sw.batch.launch()
+    torch.cuda.synchronize()
+    cands = sw.batch.select(sq[0], sq[1], 3, as_dicts=False)
+    if net is None:
+        return cands, None
+    tops, tbs = [], []
+    for m in sw.maps:
+        ta, tb = (m["plan"].n_k + 63) // 64, (m["plan"].n_x0 + 63) // 64
+        tops.append(max(1, int(math.ceil(top_frac * ta * tb))))
+        tbs.append(tb)
+    _, best = fh.fh_batch_propose(net, sw.batch, tops)
+    return cands, [(set(b), tb) for b, tb in zip(best, tbs)]
+
+
+def map_maxima(sw: Sweep, net, sq=(8, 8), top_frac: float = 0.1) -> np.ndarray:
+    """Per map: the largest CR of all its candidates (plain pipeline) and of its
+    candidates inside the proposed tiles (learned pipeline); -inf for none."""
+    cands, props = _run_pipelines(sw, net, sq, top_frac)
+    out = np.full((len(cands), 2), -np.inf)
+    for mi, cl in enumerate(cands):
+        keep = props[mi] if props is not None else None
+        for c in cl:
+            out[mi, 0] = max(out[mi, 0], float(c["cr"]))
+            if _in_proposal(c, keep):
+                out[mi, 1] = max(out[mi, 1], float(c["cr"]))
+    return out
+
+
+def evaluate_at_fap(dev, net, faps, n_noise_sweeps: int, seed: int, sw: Optional[Sweep] = None, sq=(8, 8),
+                    top_frac: float = 0.1, amp_edges=(1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0), log=None, **kw) -> list:
+    """Efficiency of both pipelines at fixed false-alarm probabilities per map.
+    Noise-only sweeps (no injection, other seeds) give, per pipeline and per
+    entry of `faps`, the smallest CR threshold whose exceedance by a map's
+    largest candidate CR is at most that probability; an injection of `sw`
+    counts as found when a candidate within 3 bins of its true cell (inside the
+    proposed tiles, for the learned pipeline) reaches the pipeline's threshold.
+    One record per entry of `faps`, with the efficiencies also binned by the
+    injections' amplitude (`amp_edges`)."""
+    from . import learn
+    noise = []
+    for q in range(n_noise_sweeps):
+        nsw = Sweep(dev, seed=seed + 1000 + q, n_inj=0, **kw)
+        noise.append(map_maxima(nsw, net, sq, top_frac))
+        nsw.destroy()
+        if log:
+            log(f"noise sweep {q + 1}/{n_noise_sweeps}")
+    noise = np.concatenate(noise, 0)
+    own = sw is None
+    if own:
+        sw = Sweep(dev, seed=seed, **kw)
+    cands, props = _run_pipelines(sw, net, sq, top_frac)
+    # per injection: the largest CR near its true cell, over all candidates and inside the proposals
+    best = np.full((len(sw.injections), 2), -np.inf)
+    for i, (b, ti, ni, f0, k, amp, row) in enumerate(sw.injections):
+        mi = sw.map_index(b, ti, ni)
+        m = sw.maps[mi]
+        info = m["plan"].info
+        col = (f0 ** (1.0 - m["n"]) - info.x0_min) / info.dx0
+        for c in cands[mi]:
+            if math.hypot(float(c["row"]) + 0.5 - row, float(c["col"]) + 0.5 - col) <= 3.0:
+                best[i, 0] = max(best[i, 0], float(c["cr"]))
+                if _in_proposal(c, props[mi]):
+                    best[i, 1] = max(best[i, 1], float(c["cr"]))
+    amps = np.array([inj[5] for inj in sw.injections])
+    if own:
+        sw.destroy()
+    out = []
+    for fap in faps:
+        thr_p = learn.threshold_for_fap(noise[:, 0], fap)
+        thr_l = learn.threshold_for_fap(noise[:, 1], fap)
+        out.append({"fap_per_map": fap, "noise_maps": int(noise.shape[0]), "thr_plain": thr_p, "thr_learned": thr_l,
+                    "fap_plain": float(np.mean(noise[:, 0] >= thr_p)),
+                    "fap_learned": float(np.mean(noise[:, 1] >= thr_l)),
+                    "injections": int(best.shape[0]), "eff_plain": float(np.mean(best[:, 0] >= thr_p)),
+                    "eff_learned": float(np.mean(best[:, 1] >= thr_l)), "tiles_proposed_frac": top_frac,
+                    "by_amp": []})
+        for lo, hi in zip(amp_edges[:-1], amp_edges[1:]):
+            sel = (amps >= lo) & (amps < hi)
+            if sel.any():
+                out[-1]["by_amp"].append({"amp_lo": lo, "amp_hi": hi, "n": int(sel.sum()),
+                                          "eff_plain": float(np.mean(best[sel, 0] >= thr_p)),
+                                          "eff_learned": float(np.mean(best[sel, 1] >= thr_l))})
+    return out
+
+
 def main():
     import argparse
     import json

@@ -60,3 +60,41 @@ def test_reduced_sweep_on_the_paper_k_grids(dev, oracle):
     ev = sweep.evaluate(sw, None, sq=(8, 8))
     assert ev["curves"][0]["eff_plain"] > 0.5
     sw.destroy()
+
+
+def test_reduced_sweep_at_fixed_fap(dev, oracle):
+    # noise-only maps' largest candidate CR (plain pipeline) matches the
+    # oracle's selection on the oracle's maps; thresholds from those maxima keep
+    # the false-alarm fraction at or under each requested probability and
+    # rise as it falls, and efficiencies fall with them
+    import os
+    from oracle import select as oracle_select
+    from paper_1810_09784_amd import fh, sweep
+    kw = dict(n_values=(2.5, 5.0), tffts=(4.0, 8.0), n_bands=2, t_obs=1.2e4, n_k=64)
+    net = fh.CNN(max_batch=64)
+    net.set_params(np.load(os.path.join(os.path.dirname(fh.__file__), "trained", "tile_cnn.npy")))
+    nsw = sweep.Sweep(dev, seed=31, n_inj=0, **kw)
+    mx = sweep.map_maxima(nsw, net, sq=(8, 8))
+    for mi, m in enumerate(nsw.maps):
+        rp, bn = nsw.peakmaps[(m["band"], m["ti"])]
+        d = oracle.Desc(m["n"], m["tfft"], m["f_min"], m["f_max"], m["n_fft"], m["k"])
+        ref = oracle.hough(d, rp.cpu().numpy(), bn.cpu().numpy())
+        _, x0m, dx, _ = oracle.grid(d)
+        rc = oracle_select.select(ref, m["k"], x0m, dx, m["n"], 8, 8, 3)
+        want = max((c["cr"] for c in rc), default=-np.inf)
+        assert mx[mi, 0] == pytest.approx(want, rel=1e-12, abs=1e-12), mi
+        assert mx[mi, 1] <= mx[mi, 0]
+    nsw.destroy()
+    sw = sweep.Sweep(dev, seed=32, n_inj=8, amp_lo=2.0, amp_hi=6.0, **kw)
+    faps = [0.5, 0.25, 0.125]
+    res = sweep.evaluate_at_fap(dev, net, faps, 3, 33, sw=sw, sq=(8, 8), **kw)
+    sw.destroy()
+    assert [r["fap_per_map"] for r in res] == faps
+    for r in res:
+        assert r["noise_maps"] == 3 * len(sw.maps)
+        assert r["fap_plain"] <= r["fap_per_map"] and r["fap_learned"] <= r["fap_per_map"]
+        assert 0.0 <= r["eff_plain"] <= 1.0 and 0.0 <= r["eff_learned"] <= 1.0
+        assert sum(b["n"] for b in r["by_amp"]) <= r["injections"] == 8
+    for a, b in zip(res[:-1], res[1:]):
+        assert b["thr_plain"] >= a["thr_plain"] and b["thr_learned"] >= a["thr_learned"]
+        assert b["eff_plain"] <= a["eff_plain"] and b["eff_learned"] <= a["eff_learned"]
