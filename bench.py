@@ -4,17 +4,19 @@
 Workload: the large single map (n = 3, 200-1200 Hz, T_FFT = 4 s, 43200 FFTs =
 2 days, 1024 k rows on [0, k_max], 84000 x0 columns, ~1.3e7 peaks of seeded
 Exp(1) noise with 20 injections).  One step = the whole hot path on that
-peakmap, inputs resident in HBM: peak ingest (rank structure), the Hough
-transform into the differential LDS tiles, the prefix sums and the map store
-(fh_hough), then candidate selection (fh_select).  The timed steps are
-pipelined: step k's transform (one stream) overlaps step k-1's selection (a
-second stream, reading the other of two map buffers); the serial step time is
-reported beside it.
+peakmap, inputs resident in HBM: fh_hough_select, that is peak ingest (rank
+structure), the Hough transform into the differential LDS tiles with the
+prefix sums, the map store and the selection's row pass in one kernel, then
+the split-tile pass and the square reduction, and the host's CR finish of the
+candidates.  The timed steps alternate two plans (two map buffers) on two
+streams, so consecutive steps overlap on the GPU; the unfused path (fh_hough
+then fh_select), serial and pipelined, is reported beside it.
 
 Metric: FH Hough updates/s, an update being one (peak, k-row) pair, counted
 over all P * n_k pairs.  Also reported: the batched persistent launch over the
-48 uneven maps against the same maps launched one by one, the roofline of the
-dominant kernel, and the oracle timed on the host cores on a row sample.
+48 uneven maps against the same maps launched one by one, the 990-map sweep,
+the CNN, the search-layout steps, the roofline of the dominant kernel, and the
+oracle timed on the host cores.
 
 Prints one JSON line on stdout; progress goes to stderr."""
 import argparse
@@ -337,20 +339,25 @@ def main():
     ms_unfused_pipe = (time.perf_counter() - t0) / K * 1e3
 
     # (3) the timed run: fh_hough_select (the selection's row pass fused into the tile
-    # kernel's epilogue) on one stream, two plans of the same map alternating so that
-    # step k's square results are fetched on the host while step k+1 runs.  Every step
-    # does the whole hot path on its own map buffer.
+    # kernel's epilogue), two plans of the same map alternating, each on a stream of its
+    # own, so that step k's selection kernels overlap step k+1's rank build and the
+    # tail of one tile kernel the start of the next, and step k's square results are
+    # fetched on the host while step k+1 runs.  Every step does the whole hot path on
+    # its own map buffer; a plan's next step waits for its previous one on its stream.
     plans2 = [plan, fh.Plan.from_spec(spec, tile=tile)]
+    streams2 = [stream, sel_stream]
 
     def fused(n, timed):
+        streams2[1].wait_stream(streams2[0])
         for k in range(n):
             j = k & 1
             if timed:
                 fh.fh_plan_set_events(plans2[j], ev[k][0], ev[k][1])
-            fh.fh_hough_select(plans2[j], rp, bn, hmaps[j], SQ_K, SQ_X0, MIN_DK, stream=stream)
+            fh.fh_hough_select(plans2[j], rp, bn, hmaps[j], SQ_K, SQ_X0, MIN_DK, stream=streams2[j])
             if k > 0:
                 cands["list"], cands["n"] = fh.fh_select_results(plans2[1 - j], as_dicts=False)
         cands["list"], cands["n"] = fh.fh_select_results(plans2[(n - 1) & 1], as_dicts=False)
+        streams2[0].wait_stream(streams2[1])
         for p_ in plans2:
             fh.fh_plan_set_events(p_, None, None)
 
@@ -402,7 +409,8 @@ def main():
                    "tile": plan.tile, "parallelism": "1 GPU",
                    "step": "fh_hough_select: rank build, tile kernel with the selection's row pass fused "
                            "into its epilogue, split-tile selection pass, square reduction (5x5 squares, 2nd >= 3 "
-                           "rows), host CR; two plans alternate so the host finish overlaps the next step"},
+                           "rows), host CR; two plans alternate on two streams, so consecutive steps overlap "
+                           "on the GPU and the host finish overlaps the next step"},
         "stages_ms": {"step_unfused_serial": round(ms_serial, 5), "step_unfused_pipelined": round(ms_unfused_pipe, 5),
                       "hough": round(ms_hough, 5), "fused_tile_kernel": round(kern_ms, 5),
                       "select_incl_host_serial": round(ms_serial - ms_hough, 5)},

@@ -124,9 +124,11 @@ def test_fused_large_map(dev, oracle):
     _compare(got, ref)
 
 
-def test_fused_pipelined_two_plans(dev, oracle):
-    # two plans of one description alternate over four peakmaps; each call's
-    # results are fetched after the next call was enqueued
+@pytest.mark.parametrize("n_streams", [1, 2])
+def test_fused_pipelined_two_plans(dev, oracle, n_streams):
+    # two plans of one description alternate over four peakmaps, on one stream
+    # or one stream each; each call's results are fetched after the next call
+    # was enqueued
     import torch
     from paper_1810_09784_amd import fh
     from oracle import select as OS
@@ -139,12 +141,17 @@ def test_fused_pipelined_two_plans(dev, oracle):
         inputs.append((pm, torch.from_numpy(pm.row_ptr).to(dev), torch.from_numpy(pm.bin).to(dev)))
     d = oracle.Desc.from_spec(specs[0])
     nf, x0m, dx, nx = oracle.grid(d)
+    streams = [torch.cuda.current_stream()]
+    if n_streams == 2:
+        streams.append(torch.cuda.Stream())
+        streams[1].wait_stream(streams[0])  # the inputs and maps were written on the first
     results = []
     for i, (pm, rp, bn) in enumerate(inputs):
-        fh.fh_hough_select(plans[i % 2], rp, bn, maps[i % 2], 6, 4, 3)
+        fh.fh_hough_select(plans[i % 2], rp, bn, maps[i % 2], 6, 4, 3, stream=streams[i % n_streams])
         if i >= 1:
             results.append(fh.fh_select_results(plans[(i - 1) % 2]))
     results.append(fh.fh_select_results(plans[(len(inputs) - 1) % 2]))
+    streams[0].wait_stream(streams[-1])
     for (pm, _, _), (got, n) in zip(inputs, results):
         ref_map = oracle.hough(d, pm.row_ptr, pm.bin)
         _compare(got, OS.select(ref_map, specs[0].k, x0m, dx, specs[0].n, 6, 4, 3))
