@@ -631,10 +631,12 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
 
   // LDS: [A (n_f+2) doubles][C rows doubles][wave scratch x NW][ia rows][ib rows][wtot 16][flags 4][discard 64]
   //      [D rows*pitch, 16-byte aligned]
+  // (no wave scratch in the windowed-only instantiation: its pair loop has no use for it)
+  constexpr int NWS = MODE == kModeWindowed ? 0 : NW;
   double* A_s = reinterpret_cast<double*>(smem);
   double* C_s = A_s + (ALDS ? (M.n_f + 2) : 0);
   WaveScratch* wsc = reinterpret_cast<WaveScratch*>(C_s + M.rows);
-  int* ia_s = reinterpret_cast<int*>(wsc + NW);
+  int* ia_s = reinterpret_cast<int*>(wsc + NWS);
   int* ib_s = ia_s + M.rows;
   int* wtot = ib_s + M.rows;  // per-wave partial sums (16 ints)
   int* flags = wtot + 16;     // [0]: ib non-increasing over the rows, [1] [2]: union FFT range
@@ -786,17 +788,26 @@ __global__ void k_prologue(MapArgs M0, const MapArgs* __restrict__ maps, int n_m
 // rank[w * n_fft + i] as (mask << 32 | peaks below), so that the tile
 // kernel's lanes (consecutive FFTs) read it coalesced.  Maps with more words
 // than the LDS holds take the per-(FFT, word) binary search instead.
-constexpr int kPrepWaves = 8;
+// The work-group's LDS is sized to its map (at most 20 KB, 13 KB for 126
+// words), so that it fits beside a windowed tile kernel's work-group on a CU
+// and a rank build can run while another map's tiles are in flight.
+constexpr int kPrepWaves = 4;
 constexpr int kPrepMaxWords = 512;
-constexpr int kPrepLdsWords = 10240;  // 40 KB of dynamic LDS per work-group (four per CU)
+constexpr int kPrepLdsTarget = 4096;  // LDS words a group aims for (16 KB)
 constexpr int kPrepUnroll = 8;        // peaks per lane loaded ahead (512 per wavefront step)
 
 // FFTs per group: the largest power of two <= 64 whose entries (row pitch
-// F + 1 u64) fit beside the waves' scratch.
-__device__ __forceinline__ int prep_group(int n_words) {
+// F + 1 u64) fit in the target beside the waves' scratch; at least one.
+__host__ __device__ __forceinline__ int prep_group(int n_words) {
   int F = 64;
-  while (F > 1 && (F + 1) * n_words * 2 + kPrepWaves * 2 * n_words > kPrepLdsWords) F >>= 1;
+  while (F > 1 && (F + 1) * n_words * 2 + kPrepWaves * 2 * n_words > kPrepLdsTarget) F >>= 1;
   return F;
+}
+
+// Dynamic LDS of a rank-build work-group for a map of n_words words.
+static int prep_lds_bytes(int n_words) {
+  if (n_words > kPrepMaxWords) return 0;  // the per-(FFT, word) search uses none
+  return ((prep_group(n_words) + 1) * n_words * 2 + kPrepWaves * 2 * n_words) * 4;
 }
 
 // The first kPrepUnroll * 64 bins of peaks [lo, hi), one per lane and step.
@@ -1016,7 +1027,7 @@ fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStrea
                      (const MapArgs*)nullptr, 1, (const int4*)p.dClears, n_clears, p.dHead);
   if (check_launch() != FH_OK) return FH_EDEVICE;
   if (a.mode == kModeWindowed) {
-    hipLaunchKernelGGL(k_prepare, dim3(2048), dim3(kPrepWaves * 64), kPrepLdsWords * 4, s, a);
+    hipLaunchKernelGGL(k_prepare, dim3(2048), dim3(kPrepWaves * 64), prep_lds_bytes(a.n_words), s, a);
     if (check_launch() != FH_OK) return FH_EDEVICE;
   }
   if (p.ev_start && hipEventRecord(p.ev_start, s) != hipSuccess) return FH_EDEVICE;
@@ -1063,7 +1074,7 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
   fh_batch_s* b = new (std::nothrow) fh_batch_s();
   if (!b) return FH_ENOMEM;
   b->m = m;
-  int lds = 0;
+  int lds = 0, prep_lds = 0;
   double total = 0;
   bool any_windowed = false;
   // all whole-FFT maps: a kernel compiled for that mode alone, with 512-thread
@@ -1094,6 +1105,7 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
       return FH_ERANGE;
     }
     any_windowed |= a.mode == kModeWindowed;
+    if (a.mode == kModeWindowed) prep_lds = std::max(prep_lds, prep_lds_bytes(a.n_words));
     b->plans.push_back(&p);
     b->peaks.push_back(peaks[i]);
     b->maps.push_back(maps[i]);
@@ -1150,8 +1162,7 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
                        b->cap,
                        none, (const MapArgs*)b->d_maps, m, (const int4*)b->d_clears, b->n_clears, b->d_head);
     if (any_windowed)
-      hipLaunchKernelGGL(k_prepare_batch, dim3(2048), dim3(kPrepWaves * 64), kPrepLdsWords * 4, b->cap, b->d_maps,
-                         m);
+      hipLaunchKernelGGL(k_prepare_batch, dim3(2048), dim3(kPrepWaves * 64), prep_lds, b->cap, b->d_maps, m);
     if (b->mode == kModeWhole)
       hipLaunchKernelGGL((k_queue<kBatchWholeThreads, true, kModeWhole>), dim3(b->grid), dim3(kBatchWholeThreads), lds,
                          b->cap, none, (const MapArgs*)b->d_maps, (const Unit*)b->d_queue, b->n_queue, b->d_head);

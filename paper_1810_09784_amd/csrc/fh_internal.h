@@ -103,7 +103,9 @@ struct Plan {
   int64_t n_tiles() const;
 };
 
-int lds_bytes_for_shape(int n_f, int rows, int cols, int a_lds, int threads, int* pitch_out);
+// Dynamic LDS of one tile.  wave_scratch: room for the per-wave scratch that
+// the whole-FFT pair loop uses (kernels compiled for windowed maps only have none).
+int lds_bytes_for_shape(int n_f, int rows, int cols, int a_lds, int threads, int* pitch_out, int wave_scratch = 1);
 
 // Split the plan's tiles into units of about `target` cost (at most
 // tile.tsplit pieces per tile), append them (map index `mi`) to units/cost and

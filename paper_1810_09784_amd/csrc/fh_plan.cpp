@@ -23,11 +23,11 @@ static bool is_finite(double x) { return std::isfinite(x); }
 
 static int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-int lds_bytes_for_shape(int n_f, int rows, int cols, int a_lds, int threads, int* pitch_out) {
+int lds_bytes_for_shape(int n_f, int rows, int cols, int a_lds, int threads, int* pitch_out, int wave_scratch) {
   int pitch = round_up(cols + 1, 4);
   if (pitch_out) *pitch_out = pitch;
   // [A][C rows][per-wave scratch 1040 B][ia, ib rows][16 + 4 ints][64 discard ints][D rows x pitch, 16-aligned]
-  long long b = (long long)rows * pitch * 4 + (long long)rows * 8 + (long long)(threads / 64) * 1040 +
+  long long b = (long long)rows * pitch * 4 + (long long)rows * 8 + (long long)(wave_scratch ? threads / 64 : 0) * 1040 +
                 (long long)rows * 8 + 80 + 16 + 256 + 16;
   if (a_lds) b += (long long)(n_f + 2) * 8;
   return b > (1LL << 30) ? (1 << 30) : (int)b;
@@ -58,8 +58,10 @@ MapArgs Plan::args(const fh_peaks& pk, int32_t* map) const {
   a.mode = tile.mode;
   a.tiles_x = (n_x0 + tile.cols - 1) / tile.cols;
   a.tiles_y = (desc.n_k + tile.rows - 1) / tile.rows;
-  a.a_lds = (lds_bytes_for_shape(n_f, tile.rows, tile.cols, 1, tile.threads, nullptr) <= kLdsBudget) ? 1 : 0;
-  a.lds_bytes = lds_bytes_for_shape(n_f, tile.rows, tile.cols, a.a_lds, tile.threads, &a.pitch);
+  // a single map's launch compiles only its own mode's pair loop
+  const int wsc = tile.mode != kModeWindowed;
+  a.a_lds = (lds_bytes_for_shape(n_f, tile.rows, tile.cols, 1, tile.threads, nullptr, wsc) <= kLdsBudget) ? 1 : 0;
+  a.lds_bytes = lds_bytes_for_shape(n_f, tile.rows, tile.cols, a.a_lds, tile.threads, &a.pitch, wsc);
   return a;
 }
 
@@ -397,8 +399,9 @@ extern "C" fh_status fh_plan(const fh_map_desc* d, const fh_tile_cfg* cfg, fh_pl
   build_profiles(p);
   {
     int pitch;
-    const int a_lds = lds_bytes_for_shape(n_f, c.rows, c.cols, 1, c.threads, nullptr) <= kLdsBudget;
-    const int lds = lds_bytes_for_shape(n_f, c.rows, c.cols, a_lds, c.threads, &pitch);
+    const int wsc = c.mode != kModeWindowed;
+    const int a_lds = lds_bytes_for_shape(n_f, c.rows, c.cols, 1, c.threads, nullptr, wsc) <= kLdsBudget;
+    const int lds = lds_bytes_for_shape(n_f, c.rows, c.cols, a_lds, c.threads, &pitch, wsc);
     const int resident = occupancy_grid(c.threads, lds, 1 << 30, c.mode);
     split_units(p, 0, p.total_cost / (4.0 * std::max(resident, 1)), p.units, p.unit_cost, p.clears);
     // longest first
