@@ -91,6 +91,31 @@ __device__ __forceinline__ f4 mfma(typename Frag<KW>::T a, typename Frag<KW>::T 
 constexpr int kConvWaves = 8;       // output rows per group
 constexpr int kConvRowsPerWG = 16;  // output rows per work-group
 
+// LDS bank spreading.  A fragment's 16 lanes read 16 consecutive pixels of
+// the staged input (stride CIN bf16) or 16 consecutive weight rows (stride K
+// bf16) at the same offset; with those strides a multiple of 128 bytes they
+// would all hit the same banks.  So the 16-byte chunks of a pixel (of a
+// weight row) are stored permuted: chunk q at slot q ^ sw, sw taken from the
+// pixel (row) index such that the 8 lanes of each 128 bytes land on distinct
+// bank groups.
+//   pixels: VPP chunks per pixel (a power of two <= 8): sw = (P / (8 / VPP)) % VPP
+//   weight rows: K / 8 = GW * odd chunks per row, GW the largest power of two
+//   dividing it (<= 8): sw = (co / (8 / GW)) % GW
+template <int VPP>
+__device__ __forceinline__ int pix_swz(int P) {
+  static_assert(VPP == 1 || VPP == 2 || VPP == 4 || VPP == 8, "chunks per pixel");
+  return VPP == 1 ? 0 : (P / (8 / VPP)) & (VPP - 1);
+}
+template <int K>
+constexpr int row_group() {
+  return (K / 8) % 8 == 0 ? 8 : (K / 8) % 4 == 0 ? 4 : (K / 8) % 2 == 0 ? 2 : 1;
+}
+template <int K>
+__device__ __forceinline__ int row_swz(int co) {
+  constexpr int GW = row_group<K>();
+  return GW == 1 ? 0 : (co / (8 / GW)) & (GW - 1);
+}
+
 template <int CIN, int COUT, bool BWD>
 __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restrict__ in, const bf16_t* __restrict__ w,
                                                           const float* __restrict__ bias,
@@ -113,7 +138,11 @@ __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restri
   {
     const uint4* src = reinterpret_cast<const uint4*>(w);
     uint4* dst = reinterpret_cast<uint4*>(wl);
-    for (int e = tid; e < COUT * K / 8; e += NT) dst[e] = src[e];
+    constexpr int RC = K / 8;  // chunks per weight row
+    for (int e = tid; e < COUT * RC; e += NT) {
+      const int co = e / RC, kq = e - co * RC;
+      dst[co * RC + (kq ^ row_swz<K>(co))] = src[e];
+    }
   }
   const bf16_t* inb = in + (size_t)b * NPIX * CIN;
   bf16_t* ob = out + (size_t)b * NPIX * COUT;
@@ -122,12 +151,12 @@ __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restri
   for (int y0 = yb; y0 < yb + kConvRowsPerWG; y0 += kConvWaves) {
     __syncthreads();  // the previous group is done with xin
     for (int e = tid; e < ROWS * COLS * VPP; e += NT) {
-      const int v = e % VPP, col = (e / VPP) % COLS, row = e / (VPP * COLS);
+      const int v = e % VPP, P = e / VPP, col = P % COLS, row = P / COLS;
       const int y = y0 - 1 + row, x = col - 1;
       uint4 val = uint4{0u, 0u, 0u, 0u};
       if (y >= 0 && y < HW && x >= 0 && x < HW)
         val = reinterpret_cast<const uint4*>(inb + ((size_t)y * HW + x) * CIN)[v];
-      reinterpret_cast<uint4*>(xin)[e] = val;
+      reinterpret_cast<uint4*>(xin)[P * VPP + (v ^ pix_swz<VPP>(P))] = val;
     }
     __syncthreads();
     f4 acc[4][NCT];
@@ -136,18 +165,21 @@ __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restri
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) acc[pt][ct] = f4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 0; kc < K; kc += KW) {
-      const int k = kc + g * EL;
+      const int k = kc + g * EL;  // EL consecutive k inside one 16-byte chunk
       const int tap = k / CIN, ci = k % CIN;
       const int dy = tap / 3, dx = tap % 3;
+      const int kq = k >> 3, kh = k & 7, cq = ci >> 3;
       typename Frag<KW>::T bf[NCT];
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct)
-        bf[ct] = *reinterpret_cast<const typename Frag<KW>::T*>(wl + (ct * 16 + m) * K + k);
+      for (int ct = 0; ct < NCT; ++ct) {
+        const int co = ct * 16 + m;
+        bf[ct] = *reinterpret_cast<const typename Frag<KW>::T*>(wl + (co * (K / 8) + (kq ^ row_swz<K>(co))) * 8 + kh);
+      }
 #pragma unroll
       for (int pt = 0; pt < 4; ++pt) {
-        const int x = pt * 16 + m;
+        const int P = (wave + dy) * COLS + (pt * 16 + m + dx);
         const typename Frag<KW>::T af =
-            *reinterpret_cast<const typename Frag<KW>::T*>(xin + ((wave + dy) * COLS + (x + dx)) * CIN + ci);
+            *reinterpret_cast<const typename Frag<KW>::T*>(xin + (P * VPP + (cq ^ pix_swz<VPP>(P))) * 8 + kh);
 #pragma unroll
         for (int ct = 0; ct < NCT; ++ct) acc[pt][ct] = mfma<KW>(af, bf[ct], acc[pt][ct]);
       }
@@ -179,30 +211,45 @@ constexpr int conv_lds() {
 }
 
 // Weight gradient of a 3x3 convolution on the matrix cores: dW[co][k] +=
-// sum over pixels of dY[p][co] * in_col[p][k].  One work-group per tile; per
-// output row it stages dY transposed ([co][x]) and three dx-shifted,
-// transposed copies of input rows y-1..y+1 ([dx][dy][ci][x]) so that every
-// fragment is one aligned LDS read; the tile's partial sums are added into
-// dW (and dbias) with atomics at the end.
+// sum over pixels of dY[p][co] * in_col[p][k].  Grid (tile, dx): a
+// work-group takes one tile and the three taps of one column offset dx.  Per
+// output row it stages dY transposed ([co][x]) and the input rows y-1..y+1
+// shifted by dx and transposed ([dy][ci][x], zero outside the tile), so that
+// every fragment is one aligned LDS read; the partial sums are added into dW
+// (and, for dx = 0, dbias) with atomics at the end.  Each wavefront owns a
+// quarter of the work-group's K tiles for every output-channel tile, so each
+// fragment it loads feeds several MFMAs.  The transposed rows are 128 bytes
+// (64 pixels) long; their 16-byte chunks sit at slot chunk ^ tsw(row), so
+// that 16 consecutive rows read at one chunk, and the staging stores of rows
+// 8 apart, spread over the banks.
+__device__ __forceinline__ int tsw(int r) { return (r ^ (r >> 3)) & 7; }
+__device__ __forceinline__ int tidx(int r, int x) {  // element (r, x) of a transposed [rows][64] array
+  return r * HW + (((x >> 3) ^ tsw(r)) << 3) + (x & 7);
+}
+
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ in, const bf16_t* __restrict__ dy,
                                                     float* __restrict__ dw, float* __restrict__ db) {
-  static_assert(CIN % 8 == 0 && COUT % 8 == 0, "16-byte staging of 8 channels");
-  constexpr int K = 9 * CIN;
-  constexpr int MT = COUT / 16, NT = K / 16, TILES = MT * NT;
-  constexpr int TPW = (TILES + 3) / 4;  // tiles per wavefront
+  static_assert(CIN % 8 == 0 && COUT % 8 == 0 && HW == 64, "16-byte staging of 8 channels, 128-byte rows");
+  constexpr int K = 9 * CIN;      // columns of dW
+  constexpr int KX = 3 * CIN;     // this work-group's columns: taps (0, dx), (1, dx), (2, dx)
+  constexpr int MT = COUT / 16, NT = KX / 16;
+  static_assert(KX % 16 == 0, "K tiles of 16");
+  constexpr int NTW = (NT + 3) / 4;  // K tiles per wavefront
   extern __shared__ __align__(16) unsigned char smem[];
   bf16_t* dyT = reinterpret_cast<bf16_t*>(smem);  // [COUT][HW]
-  bf16_t* xT = dyT + COUT * HW;                    // [3 dx][3 dy][CIN][HW]
-  const int b = blockIdx.x;
+  bf16_t* xT = dyT + COUT * HW;                    // [3 dy][CIN][HW]
+  const int b = blockIdx.x, ddx = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, m = lane & 15;
   const bf16_t* inb = in + (size_t)b * NPIX * CIN;
   const bf16_t* dyb = dy + (size_t)b * NPIX * COUT;
-  f4 acc[TPW];
+  f4 acc[MT][NTW];
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
-  float bsum = 0.f;  // dbias partial: threads 4 co .. 4 co + 3 hold channel co, 16 pixels each
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) acc[mt][j] = f4{0.f, 0.f, 0.f, 0.f};
+  float bsum = 0.f;  // dbias partial (dx = 0): threads 4 co .. 4 co + 3 hold channel co, 16 pixels each
   for (int y = 0; y < HW; ++y) {
     __syncthreads();
     // dY row y transposed.  A thread takes two adjacent pixels x, x+1 (x even)
@@ -215,21 +262,21 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
       const unsigned a[4] = {v0.x, v0.y, v0.z, v0.w}, b[4] = {v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        *reinterpret_cast<unsigned*>(dyT + (c8 + 2 * i) * HW + x) = (a[i] & 0xffffu) | (b[i] << 16);
-        *reinterpret_cast<unsigned*>(dyT + (c8 + 2 * i + 1) * HW + x) = (a[i] >> 16) | (b[i] & 0xffff0000u);
+        *reinterpret_cast<unsigned*>(dyT + tidx(c8 + 2 * i, x)) = (a[i] & 0xffffu) | (b[i] << 16);
+        *reinterpret_cast<unsigned*>(dyT + tidx(c8 + 2 * i + 1, x)) = (a[i] >> 16) | (b[i] & 0xffff0000u);
       }
     }
-    // input rows y-1 .. y+1 as three dx-shifted transposed copies: copy ddx holds
-    // X[yy][x + ddx - 1] at column x (zero outside the tile).  A thread takes a
-    // column pair (x, x+1), x even, and 8 channels: it loads the pixels x-1 ..
-    // x+2 once and stores the pair of every copy as one aligned 32-bit word.
+    // input rows y-1 .. y+1 shifted by dx and transposed: column x holds
+    // X[yy][x + dx - 1] (zero outside the tile).  A thread takes a column pair
+    // (x, x+1), x even, and 8 channels: two 16-byte loads, the pair of every
+    // channel stored as one aligned 32-bit word.
     for (int e = tid; e < 3 * (HW / 2) * (CIN / 8); e += 256) {
       const int c8 = (e % (CIN / 8)) * 8, x = ((e / (CIN / 8)) % (HW / 2)) * 2, ddy = e / ((CIN / 8) * (HW / 2));
       const int yy = y + ddy - 1;
-      unsigned px[4][4];
+      unsigned px[2][4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int xx = x - 1 + q;
+      for (int q = 0; q < 2; ++q) {
+        const int xx = x + ddx - 1 + q;
         uint4 v = uint4{0u, 0u, 0u, 0u};
         if (yy >= 0 && yy < HW && xx >= 0 && xx < HW)
           v = *reinterpret_cast<const uint4*>(inb + ((size_t)yy * HW + xx) * CIN + c8);
@@ -238,23 +285,20 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
         px[q][2] = v.z;
         px[q][3] = v.w;
       }
+      const int r0 = ddy * CIN + c8;
 #pragma unroll
-      for (int ddx = 0; ddx < 3; ++ddx) {
-        bf16_t* dst = xT + ((ddx * 3 + ddy) * CIN + c8) * HW + x;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const unsigned lo = px[ddx][i], hi = px[ddx + 1][i];  // pixels x + ddx - 1 and x + ddx
-          *reinterpret_cast<unsigned*>(dst + (2 * i) * HW) = (lo & 0xffffu) | (hi << 16);
-          *reinterpret_cast<unsigned*>(dst + (2 * i + 1) * HW) = (lo >> 16) | (hi & 0xffff0000u);
-        }
+      for (int i = 0; i < 4; ++i) {
+        const unsigned lo = px[0][i], hi = px[1][i];  // pixels x + dx - 1 and x + dx
+        *reinterpret_cast<unsigned*>(xT + tidx(r0 + 2 * i, x)) = (lo & 0xffffu) | (hi << 16);
+        *reinterpret_cast<unsigned*>(xT + tidx(r0 + 2 * i + 1, x)) = (lo >> 16) | (hi & 0xffff0000u);
       }
     }
     __syncthreads();
-    if (tid < 4 * COUT) {
-      const uint4* src = reinterpret_cast<const uint4*>(dyT + (tid >> 2) * HW + (tid & 3) * 16);
+    if (ddx == 0 && tid < 4 * COUT) {
+      const int co = tid >> 2;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const uint4 v = src[h];
+        const uint4 v = *reinterpret_cast<const uint4*>(dyT + tidx(co, (tid & 3) * 16 + h * 8));
         const unsigned w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) bsum += __uint_as_float(w[i] << 16) + __uint_as_float(w[i] & 0xffff0000u);
@@ -262,48 +306,50 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
     }
     for (int pc = 0; pc < HW; pc += 32) {  // 32 pixels per MFMA step
       const int x = pc + g * 8;
+      s8 a[MT];
 #pragma unroll
-      for (int t = 0; t < TPW; ++t) {
-        const int tile = wave * TPW + t;
-        if (tile < TILES) {
-          const int mt = tile / NT, nt = tile % NT;
-          const int co = mt * 16 + m;
-          const int k = nt * 16 + m;
-          const int tap = k / CIN, ci = k % CIN;
-          const int ddy = tap / 3, ddx = tap % 3;
-          const s8 a = *reinterpret_cast<const s8*>(dyT + co * HW + x);
-          const s8 bb = *reinterpret_cast<const s8*>(xT + ((ddx * 3 + ddy) * CIN + ci) * HW + x);
-          acc[t] = mfma<32>(a, bb, acc[t]);
+      for (int mt = 0; mt < MT; ++mt) a[mt] = *reinterpret_cast<const s8*>(dyT + tidx(mt * 16 + m, x));
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) {
+        const int nt = wave * NTW + j;
+        if (nt < NT) {
+          const s8 bb = *reinterpret_cast<const s8*>(xT + tidx(nt * 16 + m, x));  // row dy * CIN + ci
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) acc[mt][j] = mfma<32>(a[mt], bb, acc[mt][j]);
         }
       }
     }
   }
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int tile = wave * TPW + t;
-    if (tile < TILES) {
-      const int mt = tile / NT, nt = tile % NT;
+  for (int j = 0; j < NTW; ++j) {
+    const int nt = wave * NTW + j;
+    if (nt < NT) {
+      const int kx = nt * 16 + m, ddy = kx / CIN, ci = kx % CIN;
+      const int k = (ddy * 3 + ddx) * CIN + ci;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int co = mt * 16 + g * 4 + i;
-        const int k = nt * 16 + m;
-        atomicAdd(&dw[co * K + k], acc[t][i]);
-      }
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) atomicAdd(&dw[(mt * 16 + g * 4 + i) * K + k], acc[mt][j][i]);
     }
   }
-  bsum += __shfl_xor(bsum, 1);
-  bsum += __shfl_xor(bsum, 2);
-  if (tid < 4 * COUT && (tid & 3) == 0) atomicAdd(&db[tid >> 2], bsum);
+  if (ddx == 0) {
+    bsum += __shfl_xor(bsum, 1);
+    bsum += __shfl_xor(bsum, 2);
+    if (tid < 4 * COUT && (tid & 3) == 0) atomicAdd(&db[tid >> 2], bsum);
+  }
 }
 
 template <int CIN, int COUT>
 constexpr int wgrad_lds() {
-  return (COUT * HW + 9 * CIN * HW) * 2;
+  return (COUT * HW + 3 * CIN * HW) * 2;
 }
 
 // ---------------------------------------------------------- conv1 (VALU) --
-__global__ void __launch_bounds__(256) k_conv1_fwd(const bf16_t* __restrict__ in, const float* __restrict__ w1,
-                                                   const float* __restrict__ b1, bf16_t* __restrict__ out, int B) {
+// w1r: the conv1 weights already rounded to BF16 (as FP32), then the FP32
+// biases (k_round_conv1); every thread reads them at the same addresses, so
+// they come through the scalar cache.
+__global__ void __launch_bounds__(256) k_conv1_fwd(const bf16_t* __restrict__ in, const float* __restrict__ w1r,
+                                                   bf16_t* __restrict__ out, int B) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // one pixel
   if (t >= (long long)B * NPIX) return;
   const int b = (int)(t / NPIX), p = (int)(t % NPIX), y = p / HW, x = p % HW;
@@ -317,8 +363,8 @@ __global__ void __launch_bounds__(256) k_conv1_fwd(const bf16_t* __restrict__ in
 #pragma unroll
   for (int co = 0; co < C1; ++co) {
     float s = 0.f;
-    for (int tap = 0; tap < 9; ++tap) s += bf2f(f2bf(w1[co * 9 + tap])) * v[tap];
-    const unsigned h = f2bf(fmaxf(s + b1[co], 0.f));
+    for (int tap = 0; tap < 9; ++tap) s += w1r[co * 9 + tap] * v[tap];
+    const unsigned h = f2bf(fmaxf(s + w1r[NW1 + co], 0.f));
     pk[co / 2] = (co & 1) ? (pk[co / 2] | (h << 16)) : h;
   }
   uint4* o = reinterpret_cast<uint4*>(out + (size_t)t * C1);
@@ -340,10 +386,19 @@ __global__ void __launch_bounds__(256) k_conv1_wgrad(const bf16_t* __restrict__ 
       const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
       v[tap] = (yy >= 0 && yy < HW && xx >= 0 && xx < HW) ? bf2f(in[(size_t)b * NPIX + yy * HW + xx]) : 0.f;
     }
-    for (int co = 0; co < C1; ++co) {
-      const float d = bf2f(dy[((size_t)b * NPIX + p) * C1 + co]);
-      for (int tap = 0; tap < 9; ++tap) acc[co * 9 + tap] += d * v[tap];
-      acc[C1 * 9 + co] += d;
+    static_assert(C1 % 8 == 0, "16-byte loads of 8 channels");
+    const uint4* dq = reinterpret_cast<const uint4*>(dy + ((size_t)b * NPIX + p) * C1);
+#pragma unroll
+    for (int q = 0; q < C1 / 8; ++q) {
+      const uint4 u = dq[q];
+      const unsigned wd[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int co = 8 * q + e;
+        const float d = bf2f((bf16_t)(wd[e >> 1] >> (16 * (e & 1))));
+        for (int tap = 0; tap < 9; ++tap) acc[co * 9 + tap] += d * v[tap];
+        acc[C1 * 9 + co] += d;
+      }
     }
   }
   for (int e = 0; e < C1 * 9 + C1; e += C1) {
@@ -476,6 +531,13 @@ __global__ void k_pack(const float* __restrict__ src, int cin, int cout, bf16_t*
   if (wt) wt[(size_t)ci * 9 * cout + (8 - tap) * cout + co] = h;
 }
 
+// conv1's weights rounded to BF16 (kept as FP32) followed by its FP32 biases.
+__global__ void k_round_conv1(const float* __restrict__ src, float* __restrict__ w1r) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < NW1) w1r[e] = bf2f(f2bf(src[e]));
+  else if (e < NW1 + C1) w1r[e] = src[e];
+}
+
 // ---------------------------------------------------------- tile inputs --
 // Per map row: mean and 1/std of the counts over the whole row (exact int64
 // sums, FP64 statistics).
@@ -597,6 +659,7 @@ using namespace fh::cnn;
 struct fh_cnn_s {
   int max_batch = 0;
   float *params = nullptr, *grads = nullptr, *m1 = nullptr, *m2 = nullptr;
+  float* w1r = nullptr;  // conv1 weights rounded to BF16, then its biases
   bf16_t *w2 = nullptr, *w3 = nullptr, *w4 = nullptr, *w2t = nullptr, *w3t = nullptr, *w4t = nullptr;
   bf16_t *x = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *a4 = nullptr;  // activations
   bf16_t *d1 = nullptr, *d2 = nullptr, *d3 = nullptr, *d4 = nullptr;               // activation gradients
@@ -619,7 +682,7 @@ bool dalloc(T** p, size_t n) {
 
 void cnn_free(fh_cnn_s* c) {
   if (!c) return;
-  void* ptrs[] = {c->params, c->grads, c->m1,  c->m2,   c->w2,    c->w3,    c->w4, c->w2t, c->w3t, c->w4t, c->x,
+  void* ptrs[] = {c->params, c->grads, c->m1,  c->m2,   c->w1r, c->w2,    c->w3,    c->w4, c->w2t, c->w3t, c->w4t, c->x,
                   c->a1,     c->a2,    c->a3,  c->a4,   c->d1,    c->d2,    c->d3, c->d4,  c->feat, c->logit,
                   c->loss,   c->row_mean, c->row_istd, c->origins, c->ptab};
   for (void* p : ptrs)
@@ -642,7 +705,7 @@ template <int CIN, int COUT>
 fh_status launch_wgrad(const bf16_t* in, const bf16_t* dy, float* dw, float* db, int B, hipStream_t s) {
   constexpr int lds = wgrad_lds<CIN, COUT>();
   (void)hipFuncSetAttribute((const void*)k_conv_wgrad<CIN, COUT>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  hipLaunchKernelGGL((k_conv_wgrad<CIN, COUT>), dim3(B), dim3(256), lds, s, in, dy, dw, db);
+  hipLaunchKernelGGL((k_conv_wgrad<CIN, COUT>), dim3(B, 3), dim3(256), lds, s, in, dy, dw, db);
   return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
 }
 
@@ -655,6 +718,8 @@ fh_status pack(fh_cnn_s* c, hipStream_t s) {
     const int n = l.cout * 9 * l.cin;
     hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, s, c->params + l.off, l.cin, l.cout, l.w, l.wt);
   }
+  static_assert(OFF_B1 == OFF_W1 + NW1, "conv1 biases follow its weights");
+  hipLaunchKernelGGL(k_round_conv1, dim3(1), dim3(256), 0, s, c->params + OFF_W1, c->w1r);
   return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
 }
 
@@ -667,7 +732,7 @@ extern "C" fh_status fh_cnn_create(int32_t max_batch, fh_cnn_t* out) {
   c->max_batch = max_batch;
   const size_t P = (size_t)max_batch * NPIX;
   bool ok = dalloc(&c->params, NPARAM) && dalloc(&c->grads, NPARAM) && dalloc(&c->m1, NPARAM) &&
-            dalloc(&c->m2, NPARAM) && dalloc(&c->w2, NW2) && dalloc(&c->w3, NW3) && dalloc(&c->w4, NW4) &&
+            dalloc(&c->m2, NPARAM) && dalloc(&c->w1r, NW1 + C1) && dalloc(&c->w2, NW2) && dalloc(&c->w3, NW3) && dalloc(&c->w4, NW4) &&
             dalloc(&c->w2t, NW2) && dalloc(&c->w3t, NW3) && dalloc(&c->w4t, NW4) && dalloc(&c->x, P) &&
             dalloc(&c->a1, P * C1) && dalloc(&c->a2, P * C2) && dalloc(&c->a3, P * C3) && dalloc(&c->a4, P * C4) &&
             dalloc(&c->d1, P * C1) && dalloc(&c->d2, P * C2) && dalloc(&c->d3, P * C3) && dalloc(&c->d4, P * C4) &&
@@ -678,7 +743,8 @@ extern "C" fh_status fh_cnn_create(int32_t max_batch, fh_cnn_t* out) {
     return FH_ENOMEM;
   }
   if (hipMemset(c->params, 0, NPARAM * 4) != hipSuccess || hipMemset(c->m1, 0, NPARAM * 4) != hipSuccess ||
-      hipMemset(c->m2, 0, NPARAM * 4) != hipSuccess || hipMemset(c->grads, 0, NPARAM * 4) != hipSuccess) {
+      hipMemset(c->m2, 0, NPARAM * 4) != hipSuccess || hipMemset(c->grads, 0, NPARAM * 4) != hipSuccess ||
+      pack(c, nullptr) != FH_OK || hipDeviceSynchronize() != hipSuccess) {
     cnn_free(c);
     return FH_EDEVICE;
   }
@@ -720,8 +786,7 @@ extern "C" fh_status fh_cnn_forward(fh_cnn_t h, const uint16_t* tiles, int32_t B
       hipMemcpyAsync(c->x, tiles, (size_t)B * NPIX * 2, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return FH_EDEVICE;
   const long long npx = (long long)B * NPIX;
-  hipLaunchKernelGGL(k_conv1_fwd, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, c->x, c->params + OFF_W1,
-                     c->params + OFF_B1, c->a1, B);
+  hipLaunchKernelGGL(k_conv1_fwd, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, c->x, c->w1r, c->a1, B);
   fh_status st = launch_conv<C1, C2, false>(c->a1, c->w2, c->params + OFF_B2, nullptr, c->a2, B, s);
   if (st == FH_OK) st = launch_conv<C2, C3, false>(c->a2, c->w3, c->params + OFF_B3, nullptr, c->a3, B, s);
   if (st == FH_OK) st = launch_conv<C3, C4, false>(c->a3, c->w4, c->params + OFF_B4, nullptr, c->a4, B, s);
