@@ -173,6 +173,33 @@ def test_bad_bins_skipped_and_counted(dev, oracle):
         assert_maps_equal(got, ref, "bad bins")
 
 
+@pytest.mark.parametrize("n_f", [7000, 16000, 17000])
+def test_wide_bands_every_rank_build_path(dev, oracle, n_f):
+    # windowed maps whose rank structure has 219 words (groups of 4 FFTs in the
+    # rank build), 501 words (one FFT per group, past the LDS target) and 532
+    # words (above the LDS limit: the per-(FFT, word) search), each with a
+    # negative bin first and a too-large bin last, which both paths count
+    rng = np.random.default_rng(81 + n_f)
+    spec = S.cfg_tiny(rng, n_fft=24, n_f=n_f, n_k=5, n=3.0, tfft=16.0, f_min=2000.0, kscale=0.05)
+    pm = S.make_peakmap(spec)
+    rp = pm.row_ptr.astype(np.int64)
+    b_new = np.concatenate([[-5], pm.bin[:rp[-1]], [spec.n_f + 3]]).astype(np.int32)
+    rp_new = rp + 1
+    rp_new[0] = 0
+    rp_new[-1] += 1
+    pm2 = S.Peakmap(rp_new.astype(np.int32), b_new, spec.n_fft, spec.n_f)
+    ref, bad = oracle.hough(oracle.Desc.from_spec(spec), pm2.row_ptr, pm2.bin, return_bad=True)
+    assert bad == 2
+    for tile in (None, dict(mode=2, rows=1, cols=4096, threads=256, tsplit=4),
+                 dict(mode=2, rows=2, cols=12000, threads=1024, tsplit=1)):
+        plan, got, errs = run_gpu(spec, pm2, dev, tile=tile)
+        if plan is None:
+            continue
+        assert plan.tile["mode"] == 2, plan.tile
+        assert errs == 2, (errs, plan.tile)
+        assert_maps_equal(got, ref, f"n_f={n_f} tile={plan.tile}")
+
+
 def test_empty_and_sparse_peakmaps(dev, oracle):
     rng = np.random.default_rng(80)
     spec = S.cfg_tiny(rng, n_fft=50, n_f=40, n_k=5, n=3.0, tfft=1.0, f_min=100.0)
