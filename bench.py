@@ -208,7 +208,17 @@ def run_cnn(fh, dev, stream, B=256, reps=20):
     return {"tiles_per_batch": B, "forward_ms": round(fwd, 4), "forward_tiles_per_s": B / (fwd * 1e-3),
             "forward_tflops": round(tf_fwd, 1), "train_step_ms": round(trn, 4), "train_tflops": round(tf_trn, 1),
             "peak_tflops": BF16_PEAK_TFLOPS, "forward_mfma_frac": round(tf_fwd / BF16_PEAK_TFLOPS, 4),
-            "train_mfma_frac": round(tf_trn / BF16_PEAK_TFLOPS, 4)}
+            "train_mfma_frac": round(tf_trn / BF16_PEAK_TFLOPS, 4), **_mfma_measured(tf_fwd, tf_trn)}
+
+
+def _mfma_measured(tf_fwd, tf_trn):
+    from paper_1810_09784_amd import ceilings
+    ceil = ceilings.load()
+    if not ceil:
+        return {}
+    m = ceil["tests"]["mfma_bf16_16x16x32"]["tflops"]
+    return {"measured_peak_tflops": m, "forward_frac_measured": round(tf_fwd / m, 4),
+            "train_frac_measured": round(tf_trn / m, 4)}
 
 
 def run_sweep_paper_k(fh, dev, stream, K, check_oracle):
@@ -272,7 +282,7 @@ def main():
         sys.exit(2)
     import numpy as np
     import torch
-    from paper_1810_09784_amd import fh, synth, tune
+    from paper_1810_09784_amd import ceilings, fh, synth, tune
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
@@ -402,6 +412,16 @@ def main():
             "kernel_ms": round(kern_ms, 5), "alg_bytes": alg_bytes,
             "timing": "HIP events around each tile kernel on its stream, the fused steps run on one stream so "
                       "that no other launch overlaps it"}
+    # the same figures against what the chip delivers (csrc/ceilings.hip, stored by
+    # python -m paper_1810_09784_amd.ceilings on an MI355X)
+    ceil = ceilings.load()
+    if ceil:
+        t = ceil["tests"]
+        rd = t["hbm_read_1GiB"]["gb_per_s"]
+        real = roof["traffic"] / (kern_ms * 1e-3) / 1e9 if roof["traffic"] else None
+        roof["measured_ceiling"] = {"hbm_read_gb_per_s": rd, "frac_alg_bytes": round(achieved / rd, 4),
+                                    "real_traffic_gb_per_s": round(real, 1) if real else None,
+                                    "frac_real_traffic": round(real / rd, 4) if real else None}
 
     out = {
         "metric": "FH Hough updates/s (exact int32), batched vs plain; CNN det-eff @ fixed FAP",
@@ -518,7 +538,15 @@ def main():
                            "fp64_roof": {"achieved": round(fp64, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                                          "frac": round(fp64 / FP64_PEAK_TFLOPS, 4)},
                            "lds_atomic_roof": {"achieved": round(lds, 3), "peak": round(lds_peak, 3),
-                                               "unit": "T atomic lane-ops/s", "frac": round(lds / lds_peak, 4)}}
+                                               "unit": "T atomic lane-ops/s", "frac": round(lds / lds_peak, 4),
+                                               "peak_basis": "32 lanes/clk/CU x 256 CUs x 2.4 GHz"}}
+            if ceil:
+                t = ceil["tests"]
+                f_m = t["fp64_fma"]["tflops"]
+                l_m = t["lds_atomic_add_random"]["g_lane_ops_per_s"] / 1e3
+                out["work"]["fp64_roof"].update(measured_peak=f_m, frac_measured=round(fp64 / f_m, 4))
+                out["work"]["lds_atomic_roof"].update(measured_peak_random=round(l_m, 3),
+                                                      frac_measured=round(lds / l_m, 4))
         log(f"oracle: {len(rows)} rows in {dt_h:.2f} s + selection {dt_s:.2f} s on {threads} threads; "
             f"parity {parity}")
         assert parity, "GPU output differs from the oracle"

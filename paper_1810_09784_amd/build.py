@@ -51,7 +51,27 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stderr)
     os.replace(tmp, LIB)
+    build_ceilings(verbose)
     return LIB
+
+
+CEILINGS = os.path.join(PKG, "_build", "fh_ceilings")
+
+
+def build_ceilings(verbose: bool = False) -> str:
+    """The measured-ceilings microbenchmark (csrc/ceilings.hip), a separate
+    executable: run it with `python -m paper_1810_09784_amd.ceilings`."""
+    os.makedirs(os.path.dirname(CEILINGS), exist_ok=True)
+    tmp = CEILINGS + ".tmp"
+    cmd = [HIPCC, "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-Wall", "-x", "hip", os.path.join(CSRC, "ceilings.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed on ceilings.hip:\n" + r.stderr)
+    os.replace(tmp, CEILINGS)
+    return CEILINGS
 
 
 if __name__ == "__main__":
