@@ -456,9 +456,10 @@ def main():
     if not a.no_batched:
         t = time.perf_counter()
         specs = synth.cfg_batched()
-        plans, peaks, maps, Ub = [], [], [], 0
+        plans, peaks, maps, pms, Ub = [], [], [], [], 0
         for s in specs:
             p = synth.make_peakmap(s)
+            pms.append(p)
             pl = fh.Plan.from_spec(s, tile=tune.lookup(s, p.n_peaks))
             plans.append(pl)
             peaks.append((torch.from_numpy(p.row_ptr).to(dev), torch.from_numpy(p.bin).to(dev)))
@@ -473,6 +474,28 @@ def main():
                           "updates_per_launch": Ub, "ms_batched": round(ms_b, 5), "ms_plain": round(ms_p, 5),
                           "updates_per_s_batched": Ub / (ms_b * 1e-3), "updates_per_s_plain": Ub / (ms_p * 1e-3),
                           "speedup_vs_plain": round(ms_p / ms_b, 3)}
+        if not a.no_cpu_baseline:
+            # every map of the batch against the oracle, and the (peak, row) pairs that
+            # land in the grid (each one +1 and one -1 LDS atomic in the tile kernel)
+            from oracle import hough as oracle
+            t = time.perf_counter()
+            pairs_b, equal_b = 0, True
+            for s, p, m in zip(specs, pms, maps):
+                ref_b, pr = oracle.hough(oracle.Desc.from_spec(s), p.row_ptr, p.bin, return_pairs=True)
+                pairs_b += pr
+                equal_b = equal_b and bool(np.array_equal(m.cpu().numpy(), ref_b))
+            s_b = ms_b * 1e-3
+            work_b = {"in_grid_pairs": pairs_b, "in_grid_fraction": round(pairs_b / Ub, 5),
+                      "in_grid_pairs_per_s": pairs_b / s_b, "lds_atomic_lane_ops_per_s": 2 * pairs_b / s_b}
+            ceil_b = ceilings.load()
+            if ceil_b:
+                l_m = ceil_b["tests"]["lds_atomic_add_random"]["g_lane_ops_per_s"] * 1e9
+                work_b["lds_atomic_frac_measured"] = round(2 * pairs_b / s_b / l_m, 4)
+            out["batched"]["work"] = work_b
+            out["batched"]["parity_vs_oracle"] = {"checked": f"all {len(specs)} maps", "equal": equal_b}
+            log(f"batched: oracle on all maps in {time.perf_counter() - t:.1f} s, parity {equal_b}, "
+                f"{pairs_b:.4e} in-grid pairs")
+            assert equal_b, "batched GPU maps differ from the oracle"
         batch.destroy()
 
     # ------------------------------------ the tile CNN on the matrix cores --
