@@ -24,6 +24,11 @@
  *     one at a time, on one stream at a time; its fh_select calls likewise.
  *     The two kinds use separate scratch, so a selection of one map may run
  *     on another stream while the plan transforms the next map.
+ *   - Different plans share nothing: their calls may run at the same time on
+ *     different streams (no kernel of the library waits on another
+ *     work-group, so overlapping launches always finish).  Two plans of one
+ *     map description alternating over two streams let one call's rank build
+ *     and selection overlap the other's tile kernel.
  *
  * The peak bin b of FFT i stands for the frequency bin [f_min + b df,
  * f_min + (b+1) df), df = 1/tfft.  Its x-image is shifted, at row r and time
