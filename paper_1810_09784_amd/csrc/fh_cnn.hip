@@ -80,7 +80,7 @@ __device__ __forceinline__ f4 mfma(typename Frag<KW>::T a, typename Frag<KW>::T 
 }
 
 // ------------------------------------------------------------ conv (GEMM) --
-// Implicit-GEMM 3x3 convolution on the matrix cores.  One work-group = 16
+// Implicit-GEMM 3x3 convolution on the matrix cores.  One work-group = 32
 // output rows of one tile, in groups of kConvWaves rows (a wavefront per row:
 // 4 pixel tiles of 16 x all output-channel tiles of 16).  The whole weight
 // matrix is staged in LDS once per work-group, and for each group the input
@@ -89,7 +89,7 @@ __device__ __forceinline__ f4 mfma(typename Frag<KW>::T a, typename Frag<KW>::T 
 //   BWD:  out = bf16(conv(in, w) * (mask > 0))   (in = dY, w = flipped w^T,
 //         mask = the forward input of the layer: the ReLU derivative)
 constexpr int kConvWaves = 8;       // output rows per group
-constexpr int kConvRowsPerWG = 16;  // output rows per work-group
+constexpr int kConvRowsPerWG = 32;  // output rows per work-group
 
 // LDS bank spreading.  A fragment's 16 lanes read 16 consecutive pixels of
 // the staged input (stride CIN bf16) or 16 consecutive weight rows (stride K
@@ -148,17 +148,47 @@ __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restri
   bf16_t* ob = out + (size_t)b * NPIX * COUT;
   const int g = lane >> 4, m = lane & 15;
   constexpr int EL = KW / 4;  // bf16 per lane per fragment
+  // Work-groups whose LDS leaves room for one per CU load a group's input rows
+  // into registers while the previous group computes and write them to LDS
+  // after it (SPT 16-byte chunks per thread); the others, two or more per CU,
+  // overlap one group's staging with another work-group's compute instead.
+  // The 64 -> 32 data gradient has no registers to spare for it (it spills).
+  constexpr int NCHUNK = ROWS * COLS * VPP;
+  constexpr bool PREFETCH = (ROWS * COLS * CIN + COUT * K) * 2 > 80 * 1024 && COUT >= CIN;
+  constexpr int SPT = PREFETCH ? (NCHUNK + NT - 1) / NT : 1;
+  uint4 pre[SPT];
+  auto chunk = [&](int y0, int e) {
+    const int v = e % VPP, P = e / VPP, col = P % COLS, row = P / COLS;
+    const int y = y0 - 1 + row, x = col - 1;
+    uint4 val = uint4{0u, 0u, 0u, 0u};
+    if (e < NCHUNK && y >= 0 && y < HW && x >= 0 && x < HW)
+      val = reinterpret_cast<const uint4*>(inb + ((size_t)y * HW + x) * CIN)[v];
+    return val;
+  };
+  auto put = [&](int e, uint4 val) {
+    const int v = e % VPP, P = e / VPP;
+    reinterpret_cast<uint4*>(xin)[P * VPP + (v ^ pix_swz<VPP>(P))] = val;
+  };
+  if constexpr (PREFETCH) {
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) pre[q] = chunk(yb, tid + q * NT);
+  }
   for (int y0 = yb; y0 < yb + kConvRowsPerWG; y0 += kConvWaves) {
     __syncthreads();  // the previous group is done with xin
-    for (int e = tid; e < ROWS * COLS * VPP; e += NT) {
-      const int v = e % VPP, P = e / VPP, col = P % COLS, row = P / COLS;
-      const int y = y0 - 1 + row, x = col - 1;
-      uint4 val = uint4{0u, 0u, 0u, 0u};
-      if (y >= 0 && y < HW && x >= 0 && x < HW)
-        val = reinterpret_cast<const uint4*>(inb + ((size_t)y * HW + x) * CIN)[v];
-      reinterpret_cast<uint4*>(xin)[P * VPP + (v ^ pix_swz<VPP>(P))] = val;
+    if constexpr (PREFETCH) {
+#pragma unroll
+      for (int q = 0; q < SPT; ++q)
+        if (tid + q * NT < NCHUNK) put(tid + q * NT, pre[q]);
+    } else {
+      for (int e = tid; e < NCHUNK; e += NT) put(e, chunk(y0, e));
     }
     __syncthreads();
+    if constexpr (PREFETCH) {
+      if (y0 + kConvWaves < yb + kConvRowsPerWG) {
+#pragma unroll
+        for (int q = 0; q < SPT; ++q) pre[q] = chunk(y0 + kConvWaves, tid + q * NT);
+      }
+    }
     f4 acc[4][NCT];
 #pragma unroll
     for (int pt = 0; pt < 4; ++pt)
