@@ -63,46 +63,108 @@ def candidates(n_x0: int, n_k: int, n_fft: int) -> List[dict]:
     return out
 
 
-def autotune(spec, pm, dev, reps: int = 10, save: bool = True, verbose: bool = False) -> dict:
-    """Time every candidate tile shape on this map; keep the fastest."""
+def autotune(spec, pm, dev, reps: int = 10, save: bool = True, verbose: bool = False, streams: int = 1,
+             select=None) -> dict:
+    """Time every candidate tile shape on this map; keep the fastest.
+
+    streams = 1 times fh_hough launches one after the other on one stream (the
+    latency of one map).  streams = 2 times two plans of the shape alternating
+    over two streams, the throughput arrangement in which one launch's rank
+    build runs beside the other's tiles; the best shape for it can differ
+    (smaller work-groups leave no LDS for the rank build beside them).
+    select = (sq_k, sq_x0, min_dk) times fh_hough_select with that selection
+    instead, each call's candidates fetched after the next call is enqueued.
+    Every candidate must produce the same map."""
     import torch
     from . import fh
+    assert streams in (1, 2)
     rp = torch.from_numpy(pm.row_ptr).to(dev)
     bn = torch.from_numpy(pm.bin).to(dev)
     ref = None
     best = None
     results = []
     n_x0 = fh.Plan.from_spec(spec).n_x0
+    outs = None
+    sts = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(streams - 1)]
     for tile in candidates(n_x0, spec.n_k, spec.n_fft):
         try:
-            plan = fh.Plan.from_spec(spec, tile=tile)
+            plans = [fh.Plan.from_spec(spec, tile=tile) for _ in range(streams)]
         except fh.FHError:
             continue
-        out = torch.empty((plan.n_k, plan.n_x0), dtype=torch.int32, device=dev)
-        for _ in range(2):
-            fh.fh_hough(plan, rp, bn, out)
+        if outs is None:
+            outs = [torch.empty((plans[0].n_k, plans[0].n_x0), dtype=torch.int32, device=dev) for _ in range(streams)]
+
+        def run(n):
+            for st in sts[1:]:
+                st.wait_stream(sts[0])
+            for q in range(n):
+                j = q % streams
+                if select is None:
+                    fh.fh_hough(plans[j], rp, bn, outs[j], sts[j])
+                    continue
+                fh.fh_hough_select(plans[j], rp, bn, outs[j], *select, stream=sts[j])
+                if q > 0:
+                    fh.fh_select_results(plans[(q - 1) % streams], as_dicts=False)
+            if select is not None:
+                fh.fh_select_results(plans[(n - 1) % streams], as_dicts=False)
+            for st in sts[1:]:
+                sts[0].wait_stream(st)
+
+        run(2 * streams)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        for _ in range(reps):
-            fh.fh_hough(plan, rp, bn, out)
+        run(reps * streams)
         e1.record()
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
+        ms = e0.elapsed_time(e1) / (reps * streams)
         if ref is None:
-            ref = out.clone()
-        elif not torch.equal(ref, out):
-            raise RuntimeError(f"tile {plan.tile} gives a different map")
-        results.append((ms, plan.tile))
+            ref = outs[0].clone()
+        if not all(torch.equal(ref, o) for o in outs):
+            raise RuntimeError(f"tile {plans[0].tile} gives a different map")
+        results.append((ms, plans[0].tile))
         if verbose:
-            print(f"  {ms:8.4f} ms  {plan.tile}", flush=True)
+            print(f"  {ms:8.4f} ms  {plans[0].tile}", flush=True)
         if best is None or ms < best[0]:
-            best = (ms, plan.tile)
-        plan.destroy()
-    entry = {"tile": best[1], "ms": best[0], "n_candidates": len(results)}
+            best = (ms, plans[0].tile)
+        for p in plans:
+            p.destroy()
+    entry = {"tile": best[1], "ms": best[0], "n_candidates": len(results), "streams": streams,
+             "timed": "fh_hough" if select is None else f"fh_hough_select{tuple(select)}"}
     if save:
         c = _load()
         c[key(spec, pm.n_peaks)] = entry
         with open(CACHE_OUT, "w") as f:
             json.dump(c, f, indent=1, sort_keys=True)
     return entry
+
+
+def main():
+    """Tune the benchmark's workloads and write the cache: the large map for
+    its timed step (fh_hough_select with 5 x 5 squares, two plans on two
+    streams), the small map and the 48 batched maps for one launch at a time
+    (their shapes serve per-map launches; a batch runs the library's own
+    shapes, which suit its shared persistent launch better)."""
+    import argparse
+    import time
+    import torch
+    from . import synth
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--only", choices=("large", "small", "batched"), default=None)
+    a = ap.parse_args()
+    dev = torch.device("cuda:0")
+    work = [("large", synth.cfg_single_large(), 2, (5, 5, 3)), ("small", synth.cfg_single_small(), 1, None)]
+    work += [("batched", s, 1, None) for s in synth.cfg_batched()]
+    for name, spec, streams, sel in work:
+        if a.only and name != a.only:
+            continue
+        pm = synth.make_peakmap(spec)
+        t = time.time()
+        e = autotune(spec, pm, dev, reps=a.reps, streams=streams, select=sel)
+        print(f"{spec.name}: {e['tile']} {e['ms']:.4f} ms of {e['n_candidates']} shapes, "
+              f"{streams} stream(s), {time.time() - t:.1f} s", flush=True)
+
+
+if __name__ == "__main__":
+    main()
