@@ -35,14 +35,15 @@ def test_cache_keys_and_lookup():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("streams", [1, 2])
-def test_autotune_small_map(streams):
+@pytest.mark.parametrize("streams,select", [(1, None), (2, None), (2, (3, 3, 3))])
+def test_autotune_small_map(streams, select):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     rng = np.random.default_rng(7)
     spec = S.cfg_tiny(rng, n_fft=300, n_f=120, n_k=40, n=3.0, tfft=2.0, f_min=300.0)
     pm = S.make_peakmap(spec)
-    e = tune.autotune(spec, pm, torch.device("cuda:0"), reps=2, save=False, streams=streams)
+    e = tune.autotune(spec, pm, torch.device("cuda:0"), reps=2, save=False, streams=streams, select=select)
     assert e["n_candidates"] >= 2 and e["ms"] > 0 and e["streams"] == streams
+    assert e["timed"] == ("fh_hough" if select is None else "fh_hough_select(3, 3, 3)")
     assert set(e["tile"]) >= {"rows", "cols", "threads", "mode", "tsplit"}
