@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 990-map sweep and the search-layout extras")
     ap.add_argument("--cpu-rows", type=int, default=0, help="k rows of the oracle sample (0: the whole map)")
+    ap.add_argument("--fap-sweeps", type=int, default=30,
+                    help="noise-only sweeps that calibrate the sweep's fixed-FAP thresholds (0: skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter scale for HBM traffic)")
     return ap.parse_args()
@@ -94,7 +96,7 @@ def timed(fn, K, W, stream):
     return e0.elapsed_time(e1) / K
 
 
-def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_oracle):
+def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_oracle, fap_sweeps=0):
     """The 990-map sweep (batched vs per-map launches, selection, CNN proposals,
     detection efficiency) and timings of the search-layout steps: a map on the
     paper's geometric k grid, coincidences of the sweep's candidates, the
@@ -112,6 +114,18 @@ def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_
     ev = sweep.evaluate(sw, net)
     log(f"sweep: batched {ms_b:.3f} ms, plain {ms_p:.3f} ms, selection {ev['select_s']:.2f} s, "
         f"proposals {ev['propose_s']:.2f} s")
+    at_fap = None
+    if fap_sweeps > 0:
+        # both pipelines at fixed false-alarm probabilities per map: thresholds from the
+        # largest candidate CR of noise-only sweeps (other seeds), then this sweep's
+        # injections scored at them (10% of the tiles proposed for the learned one)
+        t0 = time.perf_counter()
+        at_fap = sweep.evaluate_at_fap(dev, net, [0.1, 0.01, 0.001], fap_sweeps, 5, sw=sw)
+        for r in at_fap:
+            r.pop("by_amp", None)
+        log(f"sweep: fixed-FAP efficiencies from {fap_sweeps} noise sweeps in {time.perf_counter() - t0:.1f} s: " +
+            ", ".join(f"FAP {r['fap_per_map']:g}: plain {r['eff_plain']:.3f}, learned {r['eff_learned']:.3f}"
+                      for r in at_fap))
     parity = None
     if check_oracle:
         from oracle import hough as oracle
@@ -131,7 +145,7 @@ def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_
                  "updates_per_s_batched": sw.U / (ms_b * 1e-3), "updates_per_s_plain": sw.U / (ms_p * 1e-3),
                  "speedup_vs_plain": round(ms_p / ms_b, 3), "select_s": round(ev["select_s"], 3),
                  "propose_s": round(ev["propose_s"], 3), "tiles_scored": ev["tiles"],
-                 "efficiency": ev["curves"], "parity_sampled_rows": parity,
+                 "efficiency": ev["curves"], "efficiency_at_fap": at_fap, "parity_sampled_rows": parity,
                  "note": "tile CNN trained on maps of this geometry drawn with other seeds (tile_cnn_sweep.npy)"}
     sw_paper = run_sweep_paper_k(fh, dev, stream, K, check_oracle)
     # coincidences: the sweep's candidates against a second draw of the same maps'
@@ -513,7 +527,8 @@ def main():
     # ------------------------------------------- the full sweep and extras --
     if not a.no_sweep:
         out["sweep"], out["layout"] = run_sweep(fh, synth, dev, stream, cands_large=cands, spec=spec, plan=plan, rp=rp,
-                                                bn=bn, K=max(3, K // 4), check_oracle=not a.no_cpu_baseline)
+                                                bn=bn, K=max(3, K // 4), check_oracle=not a.no_cpu_baseline,
+                                                fap_sweeps=a.fap_sweeps)
 
     if a.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.int32, device=dev)
