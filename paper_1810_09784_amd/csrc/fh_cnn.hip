@@ -518,20 +518,31 @@ __global__ void __launch_bounds__(kHeadBwdThreads) k_head_bwd(const bf16_t* __re
     atomicAdd(loss, l / (float)B);
   }
   static_assert(C4 % 8 == 0, "8 channels per 16 bytes");
+  constexpr int NV = NPIX * C4 / 8, PER = NV / kHeadBwdThreads, U = 4;  // 16-byte vectors
+  static_assert(NV % kHeadBwdThreads == 0 && PER % U == 0 && kHeadBwdThreads % (C4 / 8) == 0,
+                "a thread's vectors all hold the same 8 channels");
   const uint4* a = reinterpret_cast<const uint4*>(act4 + (size_t)b * NPIX * C4);
   uint4* d = reinterpret_cast<uint4*>(dact4 + (size_t)b * NPIX * C4);
-  for (int e = threadIdx.x; e < NPIX * C4 / 8; e += kHeadBwdThreads) {
-    const int c = (e % (C4 / 8)) * 8;
-    const uint4 v = a[e];
-    const unsigned w[4] = {v.x, v.y, v.z, v.w};
-    unsigned o[4];
+  const int c = (threadIdx.x % (C4 / 8)) * 8;
+  float gw[8];  // the gradient of each of the thread's channels where act4 > 0
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float g0 = __uint_as_float(w[i] << 16) > 0.f ? dz * w5[c + 2 * i] * (1.0f / NPIX) : 0.f;
-      const float g1 = __uint_as_float(w[i] & 0xffff0000u) > 0.f ? dz * w5[c + 2 * i + 1] * (1.0f / NPIX) : 0.f;
-      o[i] = (unsigned)f2bf(g0) | ((unsigned)f2bf(g1) << 16);
+  for (int j = 0; j < 8; ++j) gw[j] = dz * w5[c + j] * (1.0f / NPIX);
+  for (int k = 0; k < PER; k += U) {
+    uint4 v[U];  // U loads in flight
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = a[threadIdx.x + (k + u) * kHeadBwdThreads];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const unsigned w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+      unsigned o[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float g0 = __uint_as_float(w[i] << 16) > 0.f ? gw[2 * i] : 0.f;
+        const float g1 = __uint_as_float(w[i] & 0xffff0000u) > 0.f ? gw[2 * i + 1] : 0.f;
+        o[i] = (unsigned)f2bf(g0) | ((unsigned)f2bf(g1) << 16);
+      }
+      d[threadIdx.x + (k + u) * kHeadBwdThreads] = uint4{o[0], o[1], o[2], o[3]};
     }
-    d[e] = uint4{o[0], o[1], o[2], o[3]};
   }
 }
 
