@@ -405,39 +405,59 @@ __global__ void __launch_bounds__(256) k_conv1_fwd(const bf16_t* __restrict__ in
 // dW1[co][tap] = sum_p dY1[p][co] * in[p + tap]; one work-group per tile.
 __global__ void __launch_bounds__(256) k_conv1_wgrad(const bf16_t* __restrict__ in, const bf16_t* __restrict__ dy,
                                                      float* __restrict__ dw, float* __restrict__ db) {
+  constexpr int NA = C1 * 9 + C1, PU = 4;  // accumulators per thread; pixels whose loads are in flight together
+  static_assert(C1 == 16 && NPIX % (256 * PU) == 0, "reduction layout: 16 channels, whole pixel steps");
+  static_assert(C1 % 8 == 0, "16-byte loads of 8 channels");
   __shared__ float part[256][C1 + 1];
-  const int b = blockIdx.x;
-  float acc[C1 * 9 + C1];
-  for (int e = 0; e < C1 * 9 + C1; ++e) acc[e] = 0.f;
-  for (int p = threadIdx.x; p < NPIX; p += 256) {
-    const int y = p / HW, x = p % HW;
-    float v[9];
-    for (int tap = 0; tap < 9; ++tap) {
-      const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
-      v[tap] = (yy >= 0 && yy < HW && xx >= 0 && xx < HW) ? bf2f(in[(size_t)b * NPIX + yy * HW + xx]) : 0.f;
-    }
-    static_assert(C1 % 8 == 0, "16-byte loads of 8 channels");
-    const uint4* dq = reinterpret_cast<const uint4*>(dy + ((size_t)b * NPIX + p) * C1);
+  __shared__ float part2[16][C1 + 1];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  float acc[NA];
+  for (int e = 0; e < NA; ++e) acc[e] = 0.f;
+  for (int p0 = tid; p0 < NPIX; p0 += 256 * PU) {
+    float v[PU][9];
+    uint4 dq[PU][C1 / 8];
 #pragma unroll
-    for (int q = 0; q < C1 / 8; ++q) {
-      const uint4 u = dq[q];
-      const unsigned wd[4] = {u.x, u.y, u.z, u.w};
+    for (int u = 0; u < PU; ++u) {  // every load of PU pixels before the first use
+      const int p = p0 + 256 * u, y = p / HW, x = p % HW;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int co = 8 * q + e;
-        const float d = bf2f((bf16_t)(wd[e >> 1] >> (16 * (e & 1))));
-        for (int tap = 0; tap < 9; ++tap) acc[co * 9 + tap] += d * v[tap];
-        acc[C1 * 9 + co] += d;
+      for (int tap = 0; tap < 9; ++tap) {
+        const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+        v[u][tap] = (yy >= 0 && yy < HW && xx >= 0 && xx < HW) ? bf2f(in[(size_t)b * NPIX + yy * HW + xx]) : 0.f;
       }
+#pragma unroll
+      for (int q = 0; q < C1 / 8; ++q) dq[u][q] = reinterpret_cast<const uint4*>(dy + ((size_t)b * NPIX + p) * C1)[q];
     }
+#pragma unroll
+    for (int u = 0; u < PU; ++u)
+#pragma unroll
+      for (int q = 0; q < C1 / 8; ++q) {
+        const unsigned wd[4] = {dq[u][q].x, dq[u][q].y, dq[u][q].z, dq[u][q].w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int co = 8 * q + e;
+          const float d = bf2f((bf16_t)(wd[e >> 1] >> (16 * (e & 1))));
+#pragma unroll
+          for (int tap = 0; tap < 9; ++tap) acc[co * 9 + tap] += d * v[u][tap];
+          acc[C1 * 9 + co] += d;
+        }
+      }
   }
-  for (int e = 0; e < C1 * 9 + C1; e += C1) {
-    for (int q = 0; q < C1; ++q) part[threadIdx.x][q] = acc[e + q];
+  // per group of 16 accumulators: 256 partials -> 16 (each thread adds 16 rows of
+  // one channel) -> 1 (16 threads), then one atomic per accumulator
+  for (int e = 0; e < NA; e += C1) {
+    for (int q = 0; q < C1; ++q) part[tid][q] = acc[e + q];
     __syncthreads();
-    if (threadIdx.x < C1) {
+    {
+      const int q = tid & 15, r0 = (tid >> 4) * 16;
       float s = 0.f;
-      for (int r = 0; r < 256; ++r) s += part[r][threadIdx.x];
-      const int idx = e + threadIdx.x;
+      for (int r = 0; r < 16; ++r) s += part[r0 + r][q];
+      part2[tid >> 4][q] = s;
+    }
+    __syncthreads();
+    if (tid < C1) {
+      float s = 0.f;
+      for (int r = 0; r < 16; ++r) s += part2[r][tid];
+      const int idx = e + tid;
       if (idx < C1 * 9) atomicAdd(&dw[idx], s); else atomicAdd(&db[idx - C1 * 9], s);
     }
     __syncthreads();
