@@ -148,15 +148,12 @@ __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restri
   bf16_t* ob = out + (size_t)b * NPIX * COUT;
   const int g = lane >> 4, m = lane & 15;
   constexpr int EL = KW / 4;  // bf16 per lane per fragment
-  // Work-groups whose LDS leaves room for one per CU load a group's input rows
-  // into registers while the previous group computes and write them to LDS
-  // after it (SPT 16-byte chunks per thread); the others, two or more per CU,
-  // overlap one group's staging with another work-group's compute instead.
-  // The 64 -> 32 data gradient has no registers to spare for it (it spills);
-  // conv3 (32 -> 64) fits two work-groups' LDS but its registers allow one.
+  // A group's input rows are loaded into registers while the previous group
+  // computes and written to LDS after it (SPT 16-byte chunks per thread), so
+  // staging overlaps the MFMA work.  The 64 -> 32 data gradient has no
+  // registers to spare for it (it spills) and stages in place.
   constexpr int NCHUNK = ROWS * COLS * VPP;
-  constexpr bool PREFETCH =
-      ((ROWS * COLS * CIN + COUT * K) * 2 > 80 * 1024 && COUT >= CIN) || (CIN == 32 && COUT == 64 && !BWD);
+  constexpr bool PREFETCH = !(CIN == 64 && COUT == 32);
   constexpr int SPT = PREFETCH ? (NCHUNK + NT - 1) / NT : 1;
   uint4 pre[SPT];
   auto chunk = [&](int y0, int e) {
