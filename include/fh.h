@@ -341,7 +341,8 @@ fh_status fh_coincide(int32_t n_seg, int32_t na, const int32_t* a_off, const fh_
  * outside b_0 - guard .. b_0 + guard (population statistics from exact sums,
  * binary64: mu = S/N, var = S2/N - mu^2, sigma = sqrt(var); sigma = 0 gives
  * CR = NaN).  Peaks with a bin outside [0, n_f) are skipped.  The plan gives
- * n, tfft, f_min and the times T_i. */
+ * n, tfft, f_min and the times T_i.  Each FFT's window of bins is found by
+ * binary search, so a non-ascending FFT leaves its contribution unspecified. */
 typedef struct {
   int32_t y, pad;            /* peaks in bin b_0 after the move */
   double mu, sigma, cr;

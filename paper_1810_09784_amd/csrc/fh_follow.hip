@@ -46,12 +46,23 @@ __global__ void __launch_bounds__(kProjThreads)
     const double bi = floor((f - f_min) * tfft);
     // the drift in bins; |bi - b0| is below n_f + 1 whenever it matters
     const double sh = bi - b0;
-    if (!(fabs(sh) < 2147483647.0)) continue;
+    // beyond these bounds no int32 bin can land within w of b0 (and the
+    // conversions below stay defined)
+    if (!(fabs(sh) < 2147483647.0) || !(fabs(b0) < 8.0e9)) continue;
     const int shift = (int)sh;
     const int lo = min(max(row_ptr[i], 0), n_peaks);
     const int hi = min(max(row_ptr[i + 1], lo), n_peaks);
-    for (int p = lo; p < hi; ++p) {
+    // the FFT's bins ascend: binary-search the first one that can land in
+    // b0 - w .. b0 + w after the move, then walk until past the window
+    const long long key_lo = (long long)shift + (long long)b0 - w, key_hi = key_lo + 2 * w;
+    int u = lo, v = hi;
+    while (u < v) {
+      const int mid = (u + v) >> 1;
+      if ((long long)bin[mid] < key_lo) u = mid + 1; else v = mid;
+    }
+    for (int p = u; p < hi; ++p) {
       const int j = bin[p];
+      if ((long long)j > key_hi) break;
       if ((unsigned)j >= (unsigned)n_f) continue;
       const long long d = (long long)j - shift - (long long)b0;  // moved bin relative to b0
       if (d >= -w && d <= w) atomicAdd(&hs[(int)d + w], 1);

@@ -40,7 +40,7 @@ def test_projection_matches_oracle_and_lifts_the_source(dev, oracle):
     ks = [c["k"] for c in cands] + [inj.k] + list(rng.uniform(0, 2 * inj.k, 8))
     f0t = torch.tensor(f0s, dtype=torch.float64, device=dev)
     kt = torch.tensor(ks, dtype=torch.float64, device=dev)
-    for w, guard in ((40, 2), (5, 0)):
+    for w, guard in ((40, 2), (5, 0), (300, 10)):  # the last window is wider than the band
         hist, res = fh.fh_project(plan, rp, bn, f0t, kt, w=w, guard=guard)
         hist = hist.cpu().numpy()
         for i, (f0, k) in enumerate(zip(f0s, ks)):
