@@ -19,44 +19,76 @@ __global__ void k_coinc_zero(int32_t* count) {
 }
 
 // Grid over the points of a; each thread finds its segment by binary search
-// over a_off (segments are contiguous in a).
+// over a_off (segments are contiguous in a).  A thread counts its pairs in a
+// first pass; a wave prefix sum of the counts and one atomic per wave
+// reserve the wave's output slots, and a second pass writes the pairs there.
+// (One atomic per pair serialised on the counter: a list matched against
+// itself has a pair for every point.)
+__device__ __forceinline__ int wave_prefix(int x) {  // inclusive, over the 64 lanes
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
 __global__ void __launch_bounds__(kCoincThreads)
     k_coinc(int n_seg, int na, const int32_t* a_off_, const fh_point* a_, int nb, const int32_t* b_off_,
             const fh_point* b_, const double* nm1_, const double* dt_, double max_d, int32_t* pairs_, double* dist_,
             int cap, int32_t* count_) {
+  static_assert(kCoincThreads % 64 == 0, "whole wavefronts");
   const gco<const int32_t> a_off = (gco<const int32_t>)a_off_;
   const gco<const int32_t> b_off = (gco<const int32_t>)b_off_;
   const gco<const fh_point> a = (gco<const fh_point>)a_;
   const gco<const fh_point> b = (gco<const fh_point>)b_;
   const int ia = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  if (ia >= na) return;
-  int lo = 0, hi = n_seg;  // last segment s with a_off[s] <= ia
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (a_off[mid] <= ia) lo = mid; else hi = mid;
+  const bool act = ia < na;  // every lane stays for the wave prefix sum
+  int b0 = 0, b1 = 0;
+  double pk = 0.0, pdx = 1.0, pdk = 1.0, xa = 0.0;
+  if (act) {
+    int lo = 0, hi = n_seg;  // last segment s with a_off[s] <= ia
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a_off[mid] <= ia) lo = mid; else hi = mid;
+    }
+    const int s = lo;
+    pk = a[ia].k;
+    pdx = a[ia].dx0;
+    pdk = a[ia].dk;
+    xa = a[ia].x0;
+    if (nm1_ && dt_) {
+      const double m = ((gco<const double>)nm1_)[s];
+      const double t = ((gco<const double>)dt_)[s];
+      xa = xa + (m * pk) * t;
+    }
+    b0 = max(b_off[s], 0);
+    b1 = min(b_off[s + 1], nb);
   }
-  const int s = lo;
-  const double pk = a[ia].k, pdx = a[ia].dx0, pdk = a[ia].dk;
-  double xa = a[ia].x0;
-  if (nm1_ && dt_) {
-    const double m = ((gco<const double>)nm1_)[s];
-    const double t = ((gco<const double>)dt_)[s];
-    xa = xa + (m * pk) * t;
-  }
-  const int b0 = max(b_off[s], 0), b1 = min(b_off[s + 1], nb);
-  for (int ib = b0; ib < b1; ++ib) {
+  auto dist = [&](int ib) {
     const double dx = (pdx + b[ib].dx0) * 0.5;
     const double dk = (pdk + b[ib].dk) * 0.5;
     const double u = (b[ib].x0 - xa) / dx;
     const double v = (b[ib].k - pk) / dk;
-    const double d = sqrt(u * u + v * v);
+    return sqrt(u * u + v * v);
+  };
+  int n = 0;
+  for (int ib = b0; ib < b1; ++ib) n += dist(ib) <= max_d;
+  const int incl = wave_prefix(n);
+  const int lane = threadIdx.x & 63;
+  int base = 0;
+  if (lane == 63) base = atomicAdd(count_, incl);  // the wave's total
+  base = __shfl(base, 63, 64);
+  int slot = base + incl - n;
+  if (n == 0 || slot >= cap) return;
+  for (int ib = b0; ib < b1 && slot < cap; ++ib) {
+    const double d = dist(ib);
     if (d <= max_d) {
-      const int slot = atomicAdd(count_, 1);
-      if (slot < cap) {
-        ((gco<int32_t>)pairs_)[2 * (size_t)slot] = ia;
-        ((gco<int32_t>)pairs_)[2 * (size_t)slot + 1] = ib;
-        if (dist_) ((gco<double>)dist_)[slot] = d;
-      }
+      ((gco<int32_t>)pairs_)[2 * (size_t)slot] = ia;
+      ((gco<int32_t>)pairs_)[2 * (size_t)slot + 1] = ib;
+      if (dist_) ((gco<double>)dist_)[slot] = d;
+      ++slot;
     }
   }
 }
