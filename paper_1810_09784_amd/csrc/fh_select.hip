@@ -214,18 +214,26 @@ __device__ __forceinline__ int find_map(const SelMap* maps, int m, int g, F firs
 }
 
 // Row pass over every map of the batch: one wavefront per (global row,
-// column segment), four per work-group.  Same sums, key and tie rule as
-// k_select_rows.
-constexpr int kBatchSelWaves = 4;
+// column segment), sixteen per work-group.  The map of the work-group's
+// first item is searched once and shared; a wavefront whose row lies in a
+// later map searches for it.  Same sums, key and tie rule as k_select_rows.
+constexpr int kBatchSelWaves = 16;
 
 __global__ void __launch_bounds__(kBatchSelWaves * 64) k_select_rows_batch(const SelMap* __restrict__ maps, int m,
                                                                            long long n_items, int sq_x0,
                                                                            unsigned long long* rows_out_) {
+  __shared__ int s_map;
   const int lane = threadIdx.x & 63;
-  const long long item = (long long)blockIdx.x * kBatchSelWaves + (threadIdx.x >> 6);
+  const long long item0 = (long long)blockIdx.x * kBatchSelWaves;
+  if (threadIdx.x == 0)
+    s_map = find_map(maps, m, (int)(item0 / sq_x0), [](const SelMap& x) { return x.row0; });
+  __syncthreads();
+  const long long item = item0 + (threadIdx.x >> 6);
   if (item >= n_items) return;  // uniform over the wavefront
   const int grow = (int)(item / sq_x0), b = (int)(item % sq_x0);
-  const SelMap M = maps[find_map(maps, m, grow, [](const SelMap& x) { return x.row0; })];
+  int mi = s_map;
+  if (grow >= maps[mi].row0 + maps[mi].n_k) mi = find_map(maps, m, grow, [](const SelMap& x) { return x.row0; });
+  const SelMap M = maps[mi];
   const int r = grow - M.row0;
   const int W = M.col_hi - M.col_lo;
   const int s0 = M.col_lo + (int)((long long)b * W / sq_x0);
