@@ -226,6 +226,17 @@ int64_t fh_cnn_num_params(void);                                    /* 60289 */
 fh_status fh_cnn_set_params(fh_cnn_t net, const float* params, int64_t n);
 /* HOST copies of the parameters and of the last backward's gradients (either may be NULL). */
 fh_status fh_cnn_get_params(fh_cnn_t net, float* params, float* grads, int64_t n);
+/* Replace the gradients that the next fh_cnn_step applies (HOST float [n] in
+ * the flat order; n = 60289).  For callers that combine gradients outside the
+ * library (several processes' gradients summed before one step) and for tests
+ * of the optimiser alone.  Synchronous.  Errors: FH_EINVAL, FH_EDEVICE. */
+fh_status fh_cnn_set_grads(fh_cnn_t net, const float* grads, int64_t n);
+/* HOST copy of the BF16 activations of the last forward: layer 0 = the input
+ * tiles [B][64][64], layer l = 1..4 = the ReLU output of conv l, NHWC
+ * [B][64][64][C_l] with C = 16, 32, 64, 64 (B of that forward; n must equal
+ * the element count).  Synchronous.  Errors: FH_EINVAL (no forward yet, layer
+ * outside 0..4, wrong n), FH_EDEVICE. */
+fh_status fh_cnn_activations(fh_cnn_t net, int32_t layer, uint16_t* out, int64_t n);
 /* logits (DEVICE float [B], may be NULL) of B <= max_batch tiles; keeps the activations. */
 fh_status fh_cnn_forward(fh_cnn_t net, const uint16_t* tiles, int32_t B, float* logits, void* stream);
 /* Mean binary cross-entropy of the last forward against labels (DEVICE float [B], 0/1)

@@ -8,7 +8,7 @@ finite differences.
 
 Network: 4 x [3x3 conv, zero padding, bias, ReLU] 1 -> 16 -> 32 -> 64 -> 64,
 global average pool, linear 64 -> 1, logistic; loss = mean binary
-cross-entropy.  Parameter vector order: w1 [16][9], b1, w2 [32][9][16], b2,
+cross-entropy; the optimiser is Adam (adam_step).  Parameter vector order: w1 [16][9], b1, w2 [32][9][16], b2,
 w3 [64][9][32], b3, w4 [64][9][64], b4, w5 [64], b5 (conv weight index
 [co][dy*3+dx][ci])."""
 import numpy as np
@@ -119,3 +119,19 @@ def init_params(rng, scale=1.0):
     th.append(rng.normal(0, 0.1, 64))
     th.append(np.zeros(1))
     return np.concatenate(th)
+
+
+def adam_step(theta, grad, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, ICLR 2015, the algorithm of their
+    Sec. 2) in float64: moving averages of the gradient and of its square,
+    each divided by its bias correction 1 - beta^t, then a step of lr times
+    the corrected mean over (square root of the corrected second moment plus
+    eps).  t counts steps from 1.  Returns new (theta, m, v); inputs are not
+    modified."""
+    g = np.asarray(grad, dtype=np.float64)
+    m = b1 * np.asarray(m, dtype=np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, dtype=np.float64) + (1.0 - b2) * (g * g)
+    m_hat = m / (1.0 - b1 ** t)
+    v_hat = v / (1.0 - b2 ** t)
+    theta = np.asarray(theta, dtype=np.float64) - lr * m_hat / (np.sqrt(v_hat) + eps)
+    return theta, m, v

@@ -837,6 +837,25 @@ extern "C" fh_status fh_cnn_get_params(fh_cnn_t h, float* host, float* grads_hos
   return FH_OK;
 }
 
+extern "C" fh_status fh_cnn_set_grads(fh_cnn_t h, const float* grads_host, int64_t n) {
+  if (!h || !grads_host || n != NPARAM) return FH_EINVAL;
+  fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);
+  if (hipDeviceSynchronize() != hipSuccess) return FH_EDEVICE;
+  return hipMemcpy(c->grads, grads_host, NPARAM * 4, hipMemcpyHostToDevice) == hipSuccess ? FH_OK : FH_EDEVICE;
+}
+
+extern "C" fh_status fh_cnn_activations(fh_cnn_t h, int32_t layer, uint16_t* out_host, int64_t n) {
+  if (!h || !out_host || layer < 0 || layer > 4) return FH_EINVAL;
+  fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);
+  if (c->last_batch < 1) return FH_EINVAL;
+  const int ch[5] = {1, C1, C2, C3, C4};
+  const bf16_t* src[5] = {c->x, c->a1, c->a2, c->a3, c->a4};
+  const int64_t want = (int64_t)c->last_batch * NPIX * ch[layer];
+  if (n != want) return FH_EINVAL;
+  if (hipDeviceSynchronize() != hipSuccess) return FH_EDEVICE;
+  return hipMemcpy(out_host, src[layer], (size_t)want * 2, hipMemcpyDeviceToHost) == hipSuccess ? FH_OK : FH_EDEVICE;
+}
+
 extern "C" fh_status fh_cnn_forward(fh_cnn_t h, const uint16_t* tiles, int32_t B, float* logits, void* stream) {
   if (!h || !tiles || B < 1) return FH_EINVAL;
   fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);

@@ -101,6 +101,8 @@ SIGNATURES = {
     "fh_cnn_forward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "fh_cnn_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "fh_cnn_step": (C.c_int, [C.c_void_p, C.c_float, C.c_void_p]),
+    "fh_cnn_set_grads": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "fh_cnn_activations": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
     "fh_tiles": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
     "fh_propose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
@@ -443,6 +445,20 @@ class CNN:
         g = np.empty(self.n_params, dtype=np.float32)
         _check(lib().fh_cnn_get_params(self.handle, p.ctypes.data, g.ctypes.data, p.size), "fh_cnn_get_params")
         return p, g
+
+    def set_grads(self, grads):
+        """Replace the gradients the next step applies (host float array of n_params)."""
+        a = np.ascontiguousarray(grads, dtype=np.float32)
+        assert a.size == self.n_params
+        _check(lib().fh_cnn_set_grads(self.handle, a.ctypes.data, a.size), "fh_cnn_set_grads")
+
+    def activations(self, layer: int, batch: int):
+        """BF16 activations of the last forward (layer 0: input, 1..4: conv outputs)
+        as a float32 array [batch, 64, 64, C]."""
+        ch = (1, 16, 32, 64, 64)[layer]
+        raw = np.empty(batch * 64 * 64 * ch, dtype=np.uint16)
+        _check(lib().fh_cnn_activations(self.handle, int(layer), raw.ctypes.data, raw.size), "fh_cnn_activations")
+        return (raw.astype(np.uint32) << 16).view(np.float32).reshape(batch, 64, 64, ch)
 
     def forward(self, tiles, out=None, stream=None):
         """tiles: bfloat16 CUDA tensor [B, 64, 64]; returns float32 logits [B]."""

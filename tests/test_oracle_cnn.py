@@ -69,3 +69,68 @@ def test_exact_gradients_match_finite_differences():
 
 def test_parameter_count():
     assert N.init_params(np.random.default_rng(0)).size == 60289
+
+
+# --- the optimiser (Adam, Kingma and Ba 2015) -------------------------------
+
+def _run_adam(grads, lr, p0=None, **kw):
+    p = np.zeros(grads[0].shape) if p0 is None else np.array(p0, dtype=np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    out = []
+    for t, g in enumerate(grads, start=1):
+        p, m, v = N.adam_step(p, g, m, v, t, lr, **kw)
+        out.append(p.copy())
+    return out
+
+
+def test_adam_first_step_moves_by_lr_times_sign():
+    # from zero moments the corrected mean is g and the corrected second moment
+    # g^2, so the first step is lr * g / (|g| + eps): about lr in the direction -g
+    g = np.array([3.0, -0.5, 1e-3, -2e-6, 0.0])
+    (p1,) = _run_adam([g], lr=0.01)
+    assert np.allclose(p1, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-13, atol=0)
+    assert np.allclose(p1[:3], [-0.01, 0.01, -0.01], rtol=1e-4)
+    assert p1[4] == 0.0
+
+
+def test_adam_constant_gradient_moves_linearly():
+    # a constant gradient keeps both corrected moments at g and g^2 for every t
+    g = np.array([0.7, -4.0, 2.5e-3])
+    ps = _run_adam([g] * 12, lr=2e-3, p0=[1.0, 2.0, 3.0])
+    for t, p in enumerate(ps, start=1):
+        assert np.allclose(p, np.array([1.0, 2.0, 3.0]) - t * 2e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+
+
+def test_adam_zero_gradient_and_symmetries():
+    rng = np.random.default_rng(11)
+    grads = [rng.normal(size=40) * 10.0 ** rng.uniform(-6, 1, 40) for _ in range(7)]
+    base = _run_adam(grads, lr=1e-3)
+    # negating every gradient negates the path
+    neg = _run_adam([-g for g in grads], lr=1e-3)
+    assert all(np.allclose(a, -b, rtol=1e-12, atol=0) for a, b in zip(base, neg))
+    # with eps = 0 the update does not depend on the gradients' scale
+    s0 = _run_adam(grads, lr=1e-3, eps=0.0)
+    s1 = _run_adam([37.0 * g for g in grads], lr=1e-3, eps=0.0)
+    assert all(np.allclose(a, b, rtol=1e-12, atol=1e-18) for a, b in zip(s0, s1))
+    # but with eps > 0 tiny gradients move less than large ones (eps is outside the root)
+    tiny = _run_adam([np.full(3, 1e-9)], lr=1.0)[0]
+    assert np.allclose(tiny, -1e-9 / (1e-9 + 1e-8), rtol=1e-12)
+    # a zero gradient never moves a parameter, before or after other steps
+    zero = _run_adam([np.zeros(5)] * 4, lr=0.1, p0=np.arange(5.0))
+    assert all(np.array_equal(p, np.arange(5.0)) for p in zero)
+
+
+def test_adam_impulse_response():
+    # a single unit gradient at step 1, zeros after: the moments decay
+    # geometrically, m_t = b^(t-1) (1 - b) for each average, so the corrected
+    # ratio at step t is b1^(t-1)(1-b1)/(1-b1^t) over the root of
+    # b2^(t-1)(1-b2)/(1-b2^t) (this separates the roles of b1 and b2)
+    b1, b2, lr = 0.9, 0.999, 1e-2
+    ps = _run_adam([np.ones(1)] + [np.zeros(1)] * 9, lr=lr)
+    prev = 0.0
+    for t, p in enumerate(ps, start=1):
+        mh = b1 ** (t - 1) * (1 - b1) / (1 - b1 ** t)
+        vh = b2 ** (t - 1) * (1 - b2) / (1 - b2 ** t)
+        assert np.isclose(prev - p[0], lr * mh / (np.sqrt(vh) + 1e-8), rtol=1e-12)
+        prev = p[0]
