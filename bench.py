@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the 48-map batch's graph launches (no per-map launches, no oracle): for profiling")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 990-map sweep and the search-layout extras")
     ap.add_argument("--cpu-rows", type=int, default=0, help="k rows of the oracle sample (0: the whole map)")
     ap.add_argument("--fap-sweeps", type=int, default=30,
@@ -270,6 +272,82 @@ def run_sweep_paper_k(fh, dev, stream, K, check_oracle):
     return out
 
 
+def run_batched(fh, synth, tune, ceilings, dev, stream, K, W, check_oracle, plain=True):
+    """The 48 uneven maps as one persistent graph launch, against the same maps
+    launched one by one (fh_hough per map with its autotuned shape); every map
+    checked against the oracle, with the in-grid pair count of each."""
+    import numpy as np
+    import torch
+    out = {}
+    t = time.perf_counter()
+    specs = synth.cfg_batched()
+    # each path with its own best shapes: the batch with the library's shapes (they
+    # suit the shared persistent launch), the per-map launches with the shapes the
+    # autotuner found for each map alone (python -m paper_1810_09784_amd.tune)
+    plans, plans_t, peaks, maps, pms, Ub = [], [], [], [], [], 0
+    for s in specs:
+        p = synth.make_peakmap(s)
+        pms.append(p)
+        pl = fh.Plan.from_spec(s)
+        plans.append(pl)
+        plans_t.append(fh.Plan.from_spec(s, tile=tune.lookup(s, p.n_peaks)))
+        peaks.append((torch.from_numpy(p.row_ptr).to(dev), torch.from_numpy(p.bin).to(dev)))
+        maps.append(torch.empty((pl.n_k, pl.n_x0), dtype=torch.int32, device=dev))
+        Ub += p.n_peaks * pl.n_k
+    batch = fh.Batch(plans, peaks, maps)
+    log(f"batched: {len(specs)} maps, U = {Ub:.4e} ({time.perf_counter() - t:.1f} s to build)")
+    ms_b, _ = timed_steps(lambda: batch.launch(stream), K, W, stream)
+    ms_p = float("nan")
+    if plain:
+        batch_t = fh.Batch(plans_t, peaks, maps)  # its per-map launches (fh_batch_launch_plain)
+        ms_p, _ = timed_steps(lambda: batch_t.launch_plain(stream), K, W, stream)
+        batch_t.destroy()
+        batch.launch(stream)  # the maps checked below are the batch's
+    log(f"batched graph {ms_b:.4f} ms, plain per-map {ms_p:.4f} ms")
+    out.update({"workload": "48 uneven maps (n x T_FFT x 2 seeds, 64 Hz bands, 2 h - 3 d, 64-1024 k)",
+                "plain": "fh_hough map by map, each with its autotuned tile shape",
+                "updates_per_launch": Ub, "ms_batched": round(ms_b, 5),
+                "updates_per_s_batched": Ub / (ms_b * 1e-3)})
+    if plain:
+        out.update({"ms_plain": round(ms_p, 5), "updates_per_s_plain": Ub / (ms_p * 1e-3),
+                    "speedup_vs_plain": round(ms_p / ms_b, 3)})
+    if check_oracle:
+        # every map of the batch against the oracle, and the (peak, row) pairs that
+        # land in the grid (each one +1 and one -1 LDS atomic in the tile kernel)
+        from oracle import hough as oracle
+        t = time.perf_counter()
+        pairs_b, equal_b = 0, True
+        for s, p, m in zip(specs, pms, maps):
+            ref_b, pr = oracle.hough(oracle.Desc.from_spec(s), p.row_ptr, p.bin, return_pairs=True)
+            pairs_b += pr
+            equal_b = equal_b and bool(np.array_equal(m.cpu().numpy(), ref_b))
+        s_b = ms_b * 1e-3
+        work_b = {"in_grid_pairs": pairs_b, "in_grid_fraction": round(pairs_b / Ub, 5),
+                  "in_grid_pairs_per_s": pairs_b / s_b, "lds_atomic_lane_ops_per_s": 2 * pairs_b / s_b}
+        ceil_b = ceilings.load()
+        if ceil_b:
+            l_m = ceil_b["tests"]["lds_atomic_add_random"]["g_lane_ops_per_s"] * 1e9
+            work_b["lds_atomic_frac_measured"] = round(2 * pairs_b / s_b / l_m, 4)
+        out["work"] = work_b
+        out["parity_vs_oracle"] = {"checked": f"all {len(specs)} maps", "equal": equal_b}
+        log(f"batched: oracle on all maps in {time.perf_counter() - t:.1f} s, parity {equal_b}, "
+            f"{pairs_b:.4e} in-grid pairs")
+        assert equal_b, "batched GPU maps differ from the oracle"
+    batch.destroy()
+    return out
+
+
+def copy_calibration():
+    """Three plain 1 GiB device copies: their FETCH_SIZE / WRITE_SIZE readings
+    scale the counters of the other kernels to bytes."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def timed_steps(step, K, W, stream):
     import torch
     for _ in range(W):
@@ -301,6 +379,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    if a.batched_only:
+        b = run_batched(fh, synth, tune, ceilings, dev, stream, a.steps, a.warmup, False, plain=False)
+        if a.copy_calibration:
+            copy_calibration()
+        print(json.dumps({"batched": b}), flush=True)
+        return
 
     # ------------------------------------------------------------ inputs --
     t = time.perf_counter()
@@ -468,57 +552,7 @@ def main():
 
     # ---------------------------------------------------- batched (48 maps) --
     if not a.no_batched:
-        t = time.perf_counter()
-        specs = synth.cfg_batched()
-        # each path with its own best shapes: the batch with the library's shapes (they
-        # suit the shared persistent launch), the per-map launches with the shapes the
-        # autotuner found for each map alone (python -m paper_1810_09784_amd.tune)
-        plans, plans_t, peaks, maps, pms, Ub = [], [], [], [], [], 0
-        for s in specs:
-            p = synth.make_peakmap(s)
-            pms.append(p)
-            pl = fh.Plan.from_spec(s)
-            plans.append(pl)
-            plans_t.append(fh.Plan.from_spec(s, tile=tune.lookup(s, p.n_peaks)))
-            peaks.append((torch.from_numpy(p.row_ptr).to(dev), torch.from_numpy(p.bin).to(dev)))
-            maps.append(torch.empty((pl.n_k, pl.n_x0), dtype=torch.int32, device=dev))
-            Ub += p.n_peaks * pl.n_k
-        batch = fh.Batch(plans, peaks, maps)
-        log(f"batched: {len(specs)} maps, U = {Ub:.4e} ({time.perf_counter() - t:.1f} s to build)")
-        ms_b, _ = timed_steps(lambda: batch.launch(stream), K, W, stream)
-        batch_t = fh.Batch(plans_t, peaks, maps)  # its per-map launches (fh_batch_launch_plain)
-        ms_p, _ = timed_steps(lambda: batch_t.launch_plain(stream), K, W, stream)
-        batch_t.destroy()
-        batch.launch(stream)  # the maps checked below are the batch's
-        log(f"batched graph {ms_b:.4f} ms, plain per-map {ms_p:.4f} ms")
-        out["batched"] = {"workload": "48 uneven maps (n x T_FFT x 2 seeds, 64 Hz bands, 2 h - 3 d, 64-1024 k)",
-                          "plain": "fh_hough map by map, each with its autotuned tile shape",
-                          "updates_per_launch": Ub, "ms_batched": round(ms_b, 5), "ms_plain": round(ms_p, 5),
-                          "updates_per_s_batched": Ub / (ms_b * 1e-3), "updates_per_s_plain": Ub / (ms_p * 1e-3),
-                          "speedup_vs_plain": round(ms_p / ms_b, 3)}
-        if not a.no_cpu_baseline:
-            # every map of the batch against the oracle, and the (peak, row) pairs that
-            # land in the grid (each one +1 and one -1 LDS atomic in the tile kernel)
-            from oracle import hough as oracle
-            t = time.perf_counter()
-            pairs_b, equal_b = 0, True
-            for s, p, m in zip(specs, pms, maps):
-                ref_b, pr = oracle.hough(oracle.Desc.from_spec(s), p.row_ptr, p.bin, return_pairs=True)
-                pairs_b += pr
-                equal_b = equal_b and bool(np.array_equal(m.cpu().numpy(), ref_b))
-            s_b = ms_b * 1e-3
-            work_b = {"in_grid_pairs": pairs_b, "in_grid_fraction": round(pairs_b / Ub, 5),
-                      "in_grid_pairs_per_s": pairs_b / s_b, "lds_atomic_lane_ops_per_s": 2 * pairs_b / s_b}
-            ceil_b = ceilings.load()
-            if ceil_b:
-                l_m = ceil_b["tests"]["lds_atomic_add_random"]["g_lane_ops_per_s"] * 1e9
-                work_b["lds_atomic_frac_measured"] = round(2 * pairs_b / s_b / l_m, 4)
-            out["batched"]["work"] = work_b
-            out["batched"]["parity_vs_oracle"] = {"checked": f"all {len(specs)} maps", "equal": equal_b}
-            log(f"batched: oracle on all maps in {time.perf_counter() - t:.1f} s, parity {equal_b}, "
-                f"{pairs_b:.4e} in-grid pairs")
-            assert equal_b, "batched GPU maps differ from the oracle"
-        batch.destroy()
+        out["batched"] = run_batched(fh, synth, tune, ceilings, dev, stream, K, W, not a.no_cpu_baseline)
 
     # ------------------------------------ the tile CNN on the matrix cores --
     if not a.no_sweep:
@@ -531,11 +565,7 @@ def main():
                                                 fap_sweeps=a.fap_sweeps)
 
     if a.copy_calibration:
-        src = torch.empty(1 << 28, dtype=torch.int32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
+        copy_calibration()
 
     # ------------------------------------- the oracle on the host cores --
     if not a.no_cpu_baseline:
