@@ -180,6 +180,19 @@ typedef struct {
 fh_status fh_select(fh_plan_t plan, const int32_t* map, const fh_select_opts* opts, fh_candidate* out, int32_t cap,
                     int32_t* n_out, void* stream);
 
+/* fh_select for callers that cannot allocate memory (code under HIP graph
+ * capture, serving loops, hosts that forbid allocation at run time): the same
+ * kernels, results and errors as fh_select, but its scratch is a fixed array
+ * of 4 MiB (524288 64-bit words) in the library's device image, one copy per
+ * GPU, held until the process ends, and the host finish works through a
+ * buffer on the stack.  It calls no allocating routine.  Needs
+ * 3 n_k sq_x0 + 6 sq_k sq_x0 <= 524288 words, else FH_ERANGE (nothing is
+ * enqueued).  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (several threads or streams) race, so serialise them.
+ * Synchronises `stream`.  Does not touch the plan's own selection scratch. */
+fh_status fh_select_noalloc(fh_plan_t plan, const int32_t* map, const fh_select_opts* opts, fh_candidate* out,
+                            int32_t cap, int32_t* n_out, void* stream);
+
 /* The transform and the selection in one pass (Sec. IV: the Hough map, then
  * its candidates): writes the same map as fh_hough and prepares the same
  * candidates as fh_select with `opts` would, without reading the map back.

@@ -18,6 +18,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "fh_internal.h"
@@ -347,12 +348,14 @@ static fh_status sel_scratch(Plan& p, const fh_select_opts& o, unsigned long lon
   return FH_OK;
 }
 
-// mu, sigma and CR of every square from its exact sums, and the candidates.
-static void emit_candidates(const Plan& p, const fh_select_opts& o, const unsigned long long* sq, fh_candidate* out,
-                            int32_t cap, int32_t* n_out) {
+// mu, sigma and CR of squares [s0, s1) from their exact sums (sq holds square
+// s0 first), and their candidates: the first ones up to cap go to out,
+// *total counts all of them.
+static void emit_squares(const Plan& p, const fh_select_opts& o, const unsigned long long* sq, int s0, int s1,
+                         fh_candidate* out, int32_t cap, int32_t* total_io) {
   const int n_k = p.desc.n_k, sq_k = o.sq_k, sq_x0 = o.sq_x0;
   const int W = o.col_hi - o.col_lo;
-  int32_t total = 0;
+  int32_t total = *total_io;
   const double inv1n = 1.0 / (1.0 - p.desc.n);
   auto emit = [&](unsigned long long key, unsigned long long col, int sqi, int second, double mu, double sigma) {
     const int y = (int)((unsigned)(key >> 32) ^ 0x80000000u);
@@ -378,23 +381,30 @@ static void emit_candidates(const Plan& p, const fh_select_opts& o, const unsign
     }
     ++total;
   };
-  for (int a = 0; a < sq_k; ++a) {
+  (void)sq_k;
+  for (int sqi = s0; sqi < s1; ++sqi) {
+    const int a = sqi / sq_x0, b = sqi - a * sq_x0;
     const long long nr = (long long)(a + 1) * n_k / sq_k - (long long)a * n_k / sq_k;
-    for (int b = 0; b < sq_x0; ++b) {
-      const long long nc = (long long)(b + 1) * W / sq_x0 - (long long)b * W / sq_x0;
-      const long long N = nr * nc;
-      const unsigned long long* e = &sq[((size_t)a * sq_x0 + b) * kSqWords];
-      if (N <= 0 || !e[2]) continue;
-      const double mu = (double)(long long)e[0] / (double)N;
-      const double ex2 = (double)(long long)e[1] / (double)N;
-      const double var = ex2 - mu * mu;
-      const double sigma = std::sqrt(var);
-      if (!(sigma > 0.0)) continue;
-      const int sqi = a * sq_x0 + b;
-      emit(e[2], e[3], sqi, 0, mu, sigma);
-      if (e[4]) emit(e[4], e[5], sqi, 1, mu, sigma);
-    }
+    const long long nc = (long long)(b + 1) * W / sq_x0 - (long long)b * W / sq_x0;
+    const long long N = nr * nc;
+    const unsigned long long* e = &sq[(size_t)(sqi - s0) * kSqWords];
+    if (N <= 0 || !e[2]) continue;
+    const double mu = (double)(long long)e[0] / (double)N;
+    const double ex2 = (double)(long long)e[1] / (double)N;
+    const double var = ex2 - mu * mu;
+    const double sigma = std::sqrt(var);
+    if (!(sigma > 0.0)) continue;
+    emit(e[2], e[3], sqi, 0, mu, sigma);
+    if (e[4]) emit(e[4], e[5], sqi, 1, mu, sigma);
   }
+  *total_io = total;
+}
+
+// All squares of a selection (square results of every square, in order).
+static void emit_candidates(const Plan& p, const fh_select_opts& o, const unsigned long long* sq, fh_candidate* out,
+                            int32_t cap, int32_t* n_out) {
+  int32_t total = 0;
+  emit_squares(p, o, sq, 0, o.sq_k * o.sq_x0, out, cap, &total);
   *n_out = total;
 }
 
@@ -419,6 +429,70 @@ extern "C" fh_status fh_select(fh_plan_t h, const int32_t* map, const fh_select_
       hipStreamSynchronize(s) != hipSuccess)
     return FH_EDEVICE;
   emit_candidates(p, r, sq.data(), out, cap, n_out);
+  return FH_OK;
+}
+
+// ------------------------------------------- selection without allocation --
+// fh_select_noalloc runs fh_select's kernels on a fixed scratch array instead
+// of the plan's grown-on-demand buffer: the row partials, then the square
+// results.  The array lives in the library's device image, one copy per GPU;
+// its device address is looked up once per device (hipGetSymbolAddress) and
+// only that address is handed to kernels and copies.  Both kernels write every
+// word they later read, so nothing has to be cleared between calls.
+constexpr size_t kNoAllocWords = size_t(1) << 19;  // 4 MiB of 64-bit words
+static __device__ __align__(256) unsigned long long scratch[kNoAllocWords];
+constexpr int kNoAllocDevices = 64;
+constexpr int kNoAllocChunk = 256;  // squares per copy into the host finish
+static unsigned long long* g_scratch_dev[kNoAllocDevices];
+static std::mutex g_scratch_mu;
+
+// Device address of this device's scratch array (current device).
+static fh_status noalloc_scratch(unsigned long long** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return FH_EDEVICE;
+  if (dev < 0 || dev >= kNoAllocDevices) return FH_ERANGE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return FH_EDEVICE;
+    g_scratch_dev[dev] = static_cast<unsigned long long*>(ptr);
+  }
+  *out = g_scratch_dev[dev];
+  return FH_OK;
+}
+
+extern "C" fh_status fh_select_noalloc(fh_plan_t h, const int32_t* map, const fh_select_opts* o, fh_candidate* out,
+                                       int32_t cap, int32_t* n_out, void* stream) {
+  if (!h || !map || !o || !n_out || cap < 0 || (cap > 0 && !out)) return FH_EINVAL;
+  const Plan& p = reinterpret_cast<const Plan&>(*h);
+  fh_select_opts r;
+  fh_status st = check_opts(p, o, &r);
+  if (st != FH_OK) return st;
+  const size_t row_words = (size_t)p.desc.n_k * r.sq_x0 * 3;
+  const size_t n_sq = (size_t)r.sq_k * r.sq_x0;
+  if (row_words + n_sq * kSqWords > kNoAllocWords) return FH_ERANGE;
+  unsigned long long* base = nullptr;
+  st = noalloc_scratch(&base);
+  if (st != FH_OK) return st;
+  unsigned long long* d_rows = base;
+  unsigned long long* d_sq = base + row_words;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_select_rows, dim3(p.desc.n_k, r.sq_x0), dim3(kSelThreads), 0, s, map, p.n_x0, r.col_lo,
+                     r.col_hi, r.sq_x0, d_rows);
+  hipLaunchKernelGGL(k_select_squares, dim3(r.sq_k, r.sq_x0), dim3(kSelThreads), 0, s, d_rows, p.desc.n_k, r.sq_k,
+                     r.sq_x0, r.min_dk, d_sq);
+  if (hipGetLastError() != hipSuccess) return FH_EDEVICE;
+  // the host finish in chunks of squares through a buffer on the stack
+  unsigned long long buf[kNoAllocChunk * kSqWords];
+  int32_t total = 0;
+  for (size_t s0 = 0; s0 < n_sq; s0 += kNoAllocChunk) {
+    const size_t s1 = std::min(n_sq, s0 + kNoAllocChunk);
+    if (hipMemcpyAsync(buf, d_sq + s0 * kSqWords, (s1 - s0) * kSqWords * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return FH_EDEVICE;
+    emit_squares(p, r, buf, (int)s0, (int)s1, out, cap, &total);
+  }
+  *n_out = total;
   return FH_OK;
 }
 

@@ -93,6 +93,8 @@ SIGNATURES = {
                                    C.c_void_p]),
     "fh_select": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SelectOpts), C.c_void_p, C.c_int32,
                             C.POINTER(C.c_int32), C.c_void_p]),
+    "fh_select_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SelectOpts), C.c_void_p, C.c_int32,
+                            C.POINTER(C.c_int32), C.c_void_p]),
     "fh_cnn_create": (C.c_int, [C.c_int32, C.POINTER(C.c_void_p)]),
     "fh_cnn_destroy": (None, [C.c_void_p]),
     "fh_cnn_num_params": (C.c_int64, []),
@@ -268,6 +270,25 @@ def fh_select(plan: Plan, hmap, sq_k: int, sq_x0: int, min_dk: int = 3, cr_thr: 
     n = C.c_int32()
     _check(lib().fh_select(plan.handle, C.c_void_p(_ptr(hmap)), C.byref(opts), buf, int(cap), C.byref(n),
                            _stream(stream)), "fh_select")
+    m = min(n.value, cap)
+    if not as_dicts:
+        import numpy as np
+        return np.ctypeslib.as_array(buf)[:m].copy(), int(n.value)
+    return [buf[i].as_dict() for i in range(m)], int(n.value)
+
+
+def fh_select_noalloc(plan: Plan, hmap, sq_k: int, sq_x0: int, min_dk: int = 3, cr_thr: float = -1e300,
+                      col_lo: int = 0, col_hi: int = 0, cap: int = None, stream=None, as_dicts: bool = True):
+    """fh_select through the allocation-free entry point (fixed scratch array in
+    the library); same arguments and results."""
+    assert hmap.is_cuda and tuple(hmap.shape) == (plan.n_k, plan.n_x0) and hmap.is_contiguous()
+    if cap is None:
+        cap = 2 * int(sq_k) * int(sq_x0)
+    opts = SelectOpts(int(sq_k), int(sq_x0), int(min_dk), int(col_lo), int(col_hi), float(cr_thr))
+    buf = (Candidate * max(1, cap))()
+    n = C.c_int32()
+    _check(lib().fh_select_noalloc(plan.handle, C.c_void_p(_ptr(hmap)), C.byref(opts), buf, int(cap), C.byref(n),
+                                   _stream(stream)), "fh_select_noalloc")
     m = min(n.value, cap)
     if not as_dicts:
         import numpy as np
