@@ -128,18 +128,7 @@ def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_
         log(f"sweep: fixed-FAP efficiencies from {fap_sweeps} noise sweeps in {time.perf_counter() - t0:.1f} s: " +
             ", ".join(f"FAP {r['fap_per_map']:g}: plain {r['eff_plain']:.3f}, learned {r['eff_learned']:.3f}"
                       for r in at_fap))
-    parity = None
-    if check_oracle:
-        from oracle import hough as oracle
-        parity = True
-        for mi in (0, len(sw.maps) // 2, len(sw.maps) - 1):
-            m = sw.maps[mi]
-            rpm, bnm = sw.peakmaps[(m["band"], m["ti"])]
-            rows = [0, 1, m["plan"].n_k // 2, m["plan"].n_k - 1]
-            d = oracle.Desc(m["n"], m["tfft"], m["f_min"], m["f_max"], m["n_fft"], m["k"])
-            ref = oracle.hough(d, rpm.cpu().numpy(), bnm.cpu().numpy(), rows=rows)
-            parity = parity and bool(np.array_equal(m["hmap"][rows].cpu().numpy(), ref))
-        assert parity, "sweep map differs from the oracle on sampled rows"
+    parity = sweep_parity(sw, seed=51) if check_oracle else None
     sweep_out = {"workload": "11 n (2..7) x T_FFT {2,4,8} s x 30 bands of 64 Hz from 100 Hz, 5 days, 256 k rows; "
                              "200 injections",
                  "maps": len(sw.maps), "peakmaps": len(sw.peakmaps), "peaks": sw.peaks_total,
@@ -147,8 +136,11 @@ def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_
                  "updates_per_s_batched": sw.U / (ms_b * 1e-3), "updates_per_s_plain": sw.U / (ms_p * 1e-3),
                  "speedup_vs_plain": round(ms_p / ms_b, 3), "select_s": round(ev["select_s"], 3),
                  "propose_s": round(ev["propose_s"], 3), "tiles_scored": ev["tiles"],
-                 "efficiency": ev["curves"], "efficiency_at_fap": at_fap, "parity_sampled_rows": parity,
+                 "efficiency": ev["curves"], "efficiency_at_fap": at_fap, "parity_vs_oracle": parity,
                  "note": "tile CNN trained on maps of this geometry drawn with other seeds (tile_cnn_sweep.npy)"}
+    if parity:
+        sweep_out.update(in_grid_pairs=parity["in_grid_pairs"],
+                         in_grid_pairs_per_s_batched=parity["in_grid_pairs"] / (ms_b * 1e-3))
     sw_paper = run_sweep_paper_k(fh, dev, stream, K, check_oracle)
     # coincidences: the sweep's candidates against a second draw of the same maps'
     # candidates is not available, so the list is joined with itself moved by one bin
@@ -237,6 +229,51 @@ def _mfma_measured(tf_fwd, tf_trn):
             "train_frac_measured": round(tf_trn / m, 4)}
 
 
+def sweep_parity(sw, seed, pct=10):
+    """Every map of a sweep against the oracle: a seeded sample of at least
+    `pct` percent of its rows compared cell by cell with the oracle's direct counts,
+    and every row's total (sum of its peaks' clipped interval widths) against
+    the GPU map's row sum; also the (peak, row) pairs that land in the grid."""
+    import numpy as np
+    import torch
+    from oracle import hough as oracle
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(seed)
+    key, rph, bnh = None, None, None
+    n_rows = n_cmp = n_maps_ok = 0
+    pairs = 0
+    rows_equal = totals_equal = True
+    for m in sw.maps:
+        if (m["band"], m["ti"]) != key:
+            key = (m["band"], m["ti"])
+            rp_d, bn_d = sw.peakmaps[key]
+            rph, bnh = rp_d.cpu().numpy(), bn_d.cpu().numpy()
+        n_k = m["plan"].n_k
+        d = oracle.Desc(m["n"], m["tfft"], m["f_min"], m["f_max"], m["n_fft"], m["k"])
+        sample = np.sort(rng.choice(n_k, max(1, -(-n_k * pct // 100)), replace=False)).astype(np.int32)
+        ref_rows, _, _ = oracle.rows_checked(d, rph, bnh, sample)
+        got_rows = m["hmap"][torch.from_numpy(sample).long().to(m["hmap"].device)].cpu().numpy()
+        _, ref_tot, ref_pairs = oracle.rows_checked(d, rph, bnh, np.arange(n_k, dtype=np.int32), with_map=False)
+        got_tot = m["hmap"].sum(dim=1, dtype=torch.int64).cpu().numpy()
+        ok_r = bool(np.array_equal(got_rows, ref_rows))
+        ok_t = bool(np.array_equal(got_tot, ref_tot))
+        rows_equal &= ok_r
+        totals_equal &= ok_t
+        n_maps_ok += ok_r and ok_t
+        n_rows += n_k
+        n_cmp += len(sample)
+        pairs += int(ref_pairs.sum())
+    out = {"checked": f"all {len(sw.maps)} maps: a seeded {pct}% sample of each map's rows cell by cell "
+                      f"({n_cmp} rows) and every row's total ({n_rows} rows) against the oracle",
+           "rows_compared": n_cmp, "rows_with_totals": n_rows, "maps_equal": n_maps_ok,
+           "sampled_rows_equal": rows_equal, "row_totals_equal": totals_equal, "equal": rows_equal and totals_equal,
+           "in_grid_pairs": pairs, "oracle_s": round(time.perf_counter() - t0, 1)}
+    log(f"sweep parity: {n_maps_ok}/{len(sw.maps)} maps equal ({n_cmp} sampled rows, {n_rows} row totals), "
+        f"{pairs:.4e} in-grid pairs, {out['oracle_s']} s")
+    assert out["equal"], "sweep maps differ from the oracle"
+    return out
+
+
 def run_sweep_paper_k(fh, dev, stream, K, check_oracle):
     """The sweep's 990 maps on the paper's k layout: each map on the geometric k
     grid of Sec. VI.B over its T_FFT level's spindown range [1/(2 T_FFT)^2,
@@ -249,25 +286,17 @@ def run_sweep_paper_k(fh, dev, stream, K, check_oracle):
     ev = sweep.evaluate(sw, None)
     log(f"sweep (paper k grids): {sum(rows)} rows ({min(rows)}-{max(rows)} per map), batched {ms_b:.3f} ms, "
         f"selection {ev['select_s']:.2f} s")
-    parity = None
-    if check_oracle:
-        from oracle import hough as oracle
-        parity = True
-        for mi in (0, len(sw.maps) // 2, len(sw.maps) - 1):
-            m = sw.maps[mi]
-            rpm, bnm = sw.peakmaps[(m["band"], m["ti"])]
-            r = [0, 1, m["plan"].n_k // 2, m["plan"].n_k - 1]
-            d = oracle.Desc(m["n"], m["tfft"], m["f_min"], m["f_max"], m["n_fft"], m["k"])
-            ref = oracle.hough(d, rpm.cpu().numpy(), bnm.cpu().numpy(), rows=r)
-            parity = parity and bool(np.array_equal(m["hmap"][r].cpu().numpy(), ref))
-        assert parity, "paper-grid sweep map differs from the oracle on sampled rows"
+    parity = sweep_parity(sw, seed=52) if check_oracle else None
     out = {"workload": "the 990 sweep maps, each on the geometric k grid of its T_FFT level "
                        "(fdot 1/(2 T_FFT)^2 .. 1/T_FFT^2); 200 injections on grid rows",
            "k_rows": int(sum(rows)), "rows_per_map": [int(min(rows)), int(max(rows))],
            "updates_per_launch": sw.U, "ms_batched": round(ms_b, 4), "updates_per_s_batched": sw.U / (ms_b * 1e-3),
            "select_s": round(ev["select_s"], 3), "efficiency_plain": [
                {k: c[k] for k in ("cr_thr", "eff_plain", "noise_cands_plain")} for c in ev["curves"]],
-           "parity_sampled_rows": parity}
+           "parity_vs_oracle": parity}
+    if parity:
+        out.update(in_grid_pairs=parity["in_grid_pairs"],
+                   in_grid_pairs_per_s_batched=parity["in_grid_pairs"] / (ms_b * 1e-3))
     sw.destroy()
     return out
 
@@ -536,6 +565,8 @@ def main():
         "data": "synthetic: seeded Exp(1) peakmap, threshold 2.5 local maxima, 20 power-law injections",
         "config": {"workload": "single map n=3, 200-1200 Hz, T_FFT=4 s, 43200 FFTs, 1024 k x 84000 x0",
                    "peaks": pm.n_peaks, "n_k": plan.n_k, "n_x0": plan.n_x0, "updates_per_step": U,
+                   "update": "one (peak, k-row) pair, counted over all P x n_k pairs, including those whose "
+                             "image misses the x0 grid (in_grid_pairs_per_s counts only the others)",
                    "tile": plan.tile, "parallelism": "1 GPU",
                    "step": "fh_hough_select: rank build, tile kernel with the selection's row pass fused "
                            "into its epilogue, split-tile selection pass, square reduction (5x5 squares, 2nd >= 3 "
@@ -609,6 +640,8 @@ def main():
             fp64 = 4.0 * in_grid / s_k / 1e12
             lds = 2.0 * in_grid / s_k / 1e12
             lds_peak = 32 * 256 * 2.4e9 / 1e12  # 32 lanes/clk/CU, 256 CUs, 2.4 GHz
+            out["in_grid_pairs_per_step"] = in_grid
+            out["in_grid_pairs_per_s"] = in_grid / (ms * 1e-3)
             out["work"] = {"in_grid_pairs": in_grid, "in_grid_fraction": round(in_grid / U, 5),
                            "in_grid_pairs_per_s": in_grid / s_k,
                            "fp64_roof": {"achieved": round(fp64, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",

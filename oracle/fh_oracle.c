@@ -200,6 +200,74 @@ int orc_hough(const orc_desc* d, const int32_t* row_ptr, const int32_t* bin, int
   return orc_hough_rows(d, row_ptr, bin, NULL, 0, out, n_bad);
 }
 
+/*
+ * Rows of a map for checking large maps: the same direct counting as
+ * orc_hough_rows_pairs, plus per-row totals, but each row stops early where
+ * the definition says nothing more can land in the grid.  For n > 1 the
+ * table A_j decreases with j (x = f^(1-n) falls as f grows) and, with k >= 0,
+ * u = fma(-C_r, T_i, A_j) can only fall as j or T_i grows (rounding is
+ * monotone).  So once a peak's u_hi is negative (its interval lies left of
+ * column 0), every later peak of that FFT lies left too; and once the lowest
+ * bin edge A_0 of an FFT is left of column 0, every later FFT is too.  These
+ * exits need the bins of every FFT strictly ascending and times ascending;
+ * when any FFT is not ascending, or n <= 1, the function takes every pair.
+ * out (may be NULL) is int32 [n_rows][n_x0]; totals[q] = number of (peak,
+ * cell) incidences of row rows[q] (the sum of its clipped interval widths);
+ * pairs[q] = number of pairs with a non-empty clipped interval.
+ */
+int orc_rows_checked(const orc_desc* d, const int32_t* row_ptr, const int32_t* bin, const int32_t* rows,
+                     int32_t n_rows, int32_t* out, int64_t* totals, int64_t* pairs_out) {
+  int n_f, n_x0;
+  double x0_min, dx0;
+  if (orc_resolve(d, &n_f, &x0_min, &dx0, &n_x0) != ORC_OK) return ORC_EINVAL;
+  double* A = (double*)malloc(sizeof(double) * (size_t)(n_f + 1));
+  double* C = (double*)malloc(sizeof(double) * (size_t)(d->n_k > 0 ? d->n_k : 1));
+  double* T = (double*)malloc(sizeof(double) * (size_t)(d->n_fft > 0 ? d->n_fft : 1));
+  if (!A || !C || !T) {
+    free(A); free(C); free(T);
+    return ORC_EINVAL;
+  }
+  orc_tables(d->n, d->tfft, d->f_min, n_f, x0_min, dx0, d->n_k, d->k, d->n_fft, d->t, A, C, T);
+  int exits = d->n > 1.0;
+  for (int i = 0; i < d->n_fft && exits; ++i) {
+    if (i > 0 && T[i] < T[i - 1]) exits = 0;
+    for (int32_t p = row_ptr[i] + 1; p < row_ptr[i + 1]; ++p)
+      if (bin[p] <= bin[p - 1]) exits = 0;
+  }
+  if (out) memset(out, 0, sizeof(int32_t) * (size_t)n_rows * (size_t)n_x0);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int q = 0; q < n_rows; ++q) {
+    const int r = rows[q];
+    int32_t* h = out ? out + (size_t)q * (size_t)n_x0 : NULL;
+    int64_t tot = 0, prs = 0;
+    int row_exit = exits && C[r] >= 0.0;
+    for (int i = 0; i < d->n_fft; ++i) {
+      if (row_exit && fma(-C[r], T[i], A[0]) < 0.0) break; /* this FFT and all later ones left of the grid */
+      for (int32_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+        int32_t j = bin[p];
+        if (j < 0 || j >= n_f) continue;
+        double u_lo = fma(-C[r], T[i], A[j + 1]);
+        double u_hi = fma(-C[r], T[i], A[j]);
+        if (row_exit && u_hi < 0.0) break; /* this peak and the rest of its FFT left of the grid */
+        double b_lo = floor(u_lo);
+        double b_hi = floor(u_hi);
+        if (b_lo < 0.0) b_lo = 0.0;
+        if (b_hi > (double)(n_x0 - 1)) b_hi = (double)(n_x0 - 1);
+        if (b_lo <= b_hi) {
+          ++prs;
+          tot += (int64_t)(b_hi - b_lo) + 1;
+          if (h)
+            for (double b = b_lo; b <= b_hi; b += 1.0) h[(int64_t)b] += 1;
+        }
+      }
+    }
+    totals[q] = tot;
+    if (pairs_out) pairs_out[q] = prs;
+  }
+  free(A); free(C); free(T);
+  return ORC_OK;
+}
+
 /* Per-pair clipped interval [b_lo, b_hi] of one (row, peak); returns its width
  * (0 if the image misses the grid).  Exposed for the tests' brute-force pins. */
 int orc_pair_interval(const orc_desc* d, int32_t r, int32_t i, int32_t j, int32_t* b_lo_out, int32_t* b_hi_out) {

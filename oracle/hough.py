@@ -50,6 +50,9 @@ def lib():
         L.orc_hough_rows_pairs.restype = C.c_int
         L.orc_hough_rows_pairs.argtypes = [C.POINTER(OrcDesc), ip, ip, ip, C.c_int32, ip, C.POINTER(C.c_int64),
                                            C.POINTER(C.c_int64)]
+        L.orc_rows_checked.restype = C.c_int
+        L.orc_rows_checked.argtypes = [C.POINTER(OrcDesc), ip, ip, ip, C.c_int32, ip, C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int64)]
         L.orc_pair_interval.restype = C.c_int
         L.orc_pair_interval.argtypes = [C.POINTER(OrcDesc), C.c_int32, C.c_int32, C.c_int32, ip, ip]
         L.orc_threads.restype = C.c_int
@@ -156,6 +159,28 @@ def hough(d: Desc, row_ptr: np.ndarray, bin_: np.ndarray, rows: Optional[Sequenc
         raise ValueError("oracle rejected the description")
     extra = ((bad.value,) if return_bad else ()) + ((pairs.value,) if return_pairs else ())
     return (out,) + extra if extra else out
+
+
+def rows_checked(d: Desc, row_ptr: np.ndarray, bin_: np.ndarray, rows: Sequence[int], with_map: bool = True):
+    """(map rows int32 [len(rows)][n_x0] or None, row totals int64, in-grid pairs
+    int64) of the listed rows, from orc_rows_checked (direct counting with the
+    early exits the ordering of the peaks allows)."""
+    nf, x0m, dx, nx = grid(d)
+    if nf < 0 or nx <= 0:
+        raise ValueError("invalid map description")
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    bn = np.ascontiguousarray(bin_, dtype=np.int32)
+    assert rp.shape[0] == d.c.n_fft + 1
+    rl = np.ascontiguousarray(rows, dtype=np.int32)
+    assert rl.size == 0 or (rl.min() >= 0 and rl.max() < d.n_k)
+    out = np.empty((rl.shape[0], nx), dtype=np.int32) if with_map else None
+    tot = np.empty(rl.shape[0], dtype=np.int64)
+    prs = np.empty(rl.shape[0], dtype=np.int64)
+    st = lib().orc_rows_checked(C.byref(d.c), _iptr(rp), _iptr(bn), _iptr(rl), rl.shape[0], _iptr(out),
+                                tot.ctypes.data_as(C.POINTER(C.c_int64)), prs.ctypes.data_as(C.POINTER(C.c_int64)))
+    if st != 0:
+        raise ValueError("oracle rejected the description")
+    return out, tot, prs
 
 
 def pair_interval(d: Desc, r: int, i: int, j: int):
