@@ -29,6 +29,11 @@
  *     work-group, so overlapping launches always finish).  Two plans of one
  *     map description alternating over two streams let one call's rank build
  *     and selection overlap the other's tile kernel.
+ *   - Fault injection for tests of callers' error paths, read at each use:
+ *     with FH_FAKE_OOM set in the environment every device allocation of the
+ *     library fails (FH_ENOMEM); FH_FAKE_DEVICE_ERROR=graph makes the graph
+ *     instantiation of fh_batch_create fail (FH_EDEVICE).  Either way the call
+ *     returns before anything is launched and frees what it had allocated.
  *
  * The peak bin b of FFT i stands for the frequency bin [f_min + b df,
  * f_min + (b+1) df), df = 1/tfft.  Its x-image is shifted, at row r and time
@@ -84,9 +89,15 @@ typedef struct {
  * windowed mode unspecified (never out-of-bounds memory access). */
 typedef struct {
   const int32_t* row_ptr;
-  const int32_t* bin;
+  const int32_t* bin;      /* 16-byte aligned (read 16 bytes at a time) */
   int64_t n_peaks;
 } fh_peaks;
+
+/* Host checks that every entry point taking peaks makes before it enqueues
+ * anything: row_ptr not NULL, 0 <= n_peaks < 2^31, bin not NULL when
+ * n_peaks > 0, and bin 16-byte aligned (torch and hipMalloc allocations are).
+ * FH_OK or FH_EINVAL; touches no memory and no device. */
+fh_status fh_peaks_validate(const fh_peaks* peaks);
 
 /* Tile shape of the Hough kernel; zeros = automatic.  mode 1 = every tile
  * reads whole FFTs (small maps), mode 2 = tiles read only the peaks whose
@@ -122,8 +133,9 @@ void fh_plan_destroy(fh_plan_t plan);
 /* The generalized FrequencyHough of one peakmap (Sec. IV): writes every cell
  * of map (DEVICE int32 [n_k][n_x0], row-major, x0 ascending = frequency
  * descending), so the caller need not clear it.  Counts are exact.
- * Errors (nothing enqueued): FH_EINVAL for NULL pointers or n_peaks < 0 or
- * n_peaks >= 2^31; FH_EDEVICE if a launch fails. */
+ * Errors (nothing enqueued): FH_EINVAL for NULL pointers or peaks failing
+ * fh_peaks_validate (sizes, a bin array that is not 16-byte aligned);
+ * FH_EDEVICE if a launch fails. */
 fh_status fh_hough(fh_plan_t plan, const fh_peaks* peaks, int32_t* map, void* stream);
 
 /* Profiling hook: when start/stop (hipEvent_t, passed as void*) are set,
@@ -132,8 +144,12 @@ fh_status fh_hough(fh_plan_t plan, const fh_peaks* peaks, int32_t* map, void* st
  * timed on the stream it runs on.  NULL, NULL clears the hook. */
 fh_status fh_plan_set_events(fh_plan_t plan, void* start, void* stop);
 
-/* Number of bad peaks (bin outside [0,n_f), or not ascending) seen by the last
- * fh_hough / batch launch of this plan.  Synchronises `stream`. */
+/* Number of bad peaks seen by the last fh_hough / batch launch of this plan:
+ * a peak is bad when its bin is outside [0, n_f) or not above the previous
+ * bin of its FFT, and each bad peak counts once.  (Bands of more than 16384
+ * bins find each FFT's words by bisection: there an FFT that is not ascending
+ * apart from out-of-band bins at its two ends counts at least one.)
+ * Synchronises `stream`. */
 fh_status fh_device_errors(fh_plan_t plan, void* stream, uint64_t* out);
 
 /* ---------------------------------------------------------- selection --

@@ -737,7 +737,10 @@ namespace {
 
 template <typename T>
 bool dalloc(T** p, size_t n) {
-  return hipMalloc((void**)p, sizeof(T) * (n ? n : 1)) == hipSuccess;
+  void* v = nullptr;
+  const bool ok = fh::device_alloc(&v, sizeof(T) * (n ? n : 1)) == FH_OK;
+  *p = static_cast<T*>(v);
+  return ok;
 }
 
 void cnn_free(fh_cnn_s* c) {

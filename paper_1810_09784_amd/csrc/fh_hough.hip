@@ -431,6 +431,7 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
     // C of tile row `lane` in each lane (rows <= 64): the row loop broadcasts it
     // with v_readlane instead of a memory load per row
     const double C_lane = G.C[r0 + min(lane, nrows - 1)];
+    int prev_last = INT_MIN;  // bin of the previous chunk's last peak (bad-peak count)
     for (int f0 = i_start + wave * kWave; f0 < i_end; f0 += NW * kWave) {
       const int nb = min(kWave, i_end - f0);
       const int fi = f0 + min(lane, nb - 1);
@@ -467,7 +468,15 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
         }
         const double T = S.T[u];
         const bool jv = pv && (unsigned)j < (unsigned)M.n_f;
-        if (count_bad && pv && !jv) atomicAdd(M.err, 1ull);
+        if (count_bad) {
+          // a bad peak: bin outside [0, n_f) or not above the previous bin of its
+          // FFT; counted once (this tile sees every peak once)
+          int jm = __shfl_up(j, 1);
+          if (lane == 0) jm = prev_last;
+          prev_last = __shfl(j, kWave - 1);
+          const bool first = pcl == S.rp[u];
+          if (pv && (!jv || (!first && j <= jm))) atomicAdd(M.err, 1ull);
+        }
         // a bad bin reads the pad entry A[n_f + 1] = +huge: an empty interval
         const int jc = (int)min((unsigned)j, (unsigned)M.n_f);
         const double a_hi = ALDS ? A_s[jc] : G.A[jc];
@@ -849,9 +858,9 @@ __device__ void prepare_fft_lds(const MapArgs& M, int lo, int hi, const int* j0,
       if (lane == 0) jm = last;
       last = __shfl(j, kWave - 1);
       if (v) {
-        bad += j <= jm;  // not ascending
-        if (j < 0 || j >= M.n_f) {
-          ++bad;
+        const bool out = j < 0 || j >= M.n_f;
+        bad += out || j <= jm;  // out of the band or not ascending: one bad peak
+        if (out) {
           neg += j < 0;
         } else {
           atomicAdd(&cnt[j >> 5], 1u);
@@ -896,8 +905,8 @@ __device__ void prepare_word(const MapArgs& M, long long t) {
   for (; q < hi; ++q) {
     const int j = G.bin[q];
     if (j >= key + 32) break;
-    if (j < M.n_f) mask |= 1u << (j & 31); else ++bad;
-    if (q > lo && G.bin[q - 1] >= j) ++bad;
+    if (j < M.n_f) mask |= 1u << (j & 31);
+    bad += j >= M.n_f || (q > lo && G.bin[q - 1] >= j);  // out of the band or not ascending: one bad peak
   }
   if (w == 0) bad += (unsigned long long)(a - lo);
   if (w == M.n_words - 1) bad += (unsigned long long)(hi - q);
@@ -1090,8 +1099,7 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
   b->threads = all_whole ? kBatchWholeThreads : 256;
   b->mode = all_whole ? (int)kModeWhole : 0;
   for (int i = 0; i < m; ++i) {
-    if (!plans[i] || !maps[i] || !peaks[i].row_ptr || peaks[i].n_peaks < 0 || peaks[i].n_peaks >= (1LL << 31) ||
-        (peaks[i].n_peaks > 0 && !peaks[i].bin)) {
+    if (!plans[i] || !maps[i] || check_peaks(&peaks[i]) != FH_OK) {
       batch_free(b);
       return FH_EINVAL;
     }
@@ -1133,12 +1141,20 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
   b->n_clears = (int32_t)clears.size();
   b->lds = lds;
   b->grid = std::max(1, std::min(resident, b->n_queue));
-  if (hipMalloc((void**)&b->d_maps, sizeof(MapArgs) * m) != hipSuccess ||
-      hipMalloc((void**)&b->d_queue, sizeof(Unit) * q.size()) != hipSuccess ||
-      hipMalloc((void**)&b->d_clears, sizeof(int4) * std::max<size_t>(1, clears.size())) != hipSuccess ||
-      hipMalloc((void**)&b->d_head, sizeof(int32_t)) != hipSuccess) {
-    batch_free(b);
-    return FH_ENOMEM;
+  {
+    void *vm = nullptr, *vq = nullptr, *vc = nullptr, *vh = nullptr;
+    fh_status st = device_alloc(&vm, sizeof(MapArgs) * m);
+    b->d_maps = static_cast<MapArgs*>(vm);
+    if (st == FH_OK) st = device_alloc(&vq, sizeof(Unit) * q.size());
+    b->d_queue = static_cast<Unit*>(vq);
+    if (st == FH_OK) st = device_alloc(&vc, sizeof(int4) * std::max<size_t>(1, clears.size()));
+    b->d_clears = static_cast<int4*>(vc);
+    if (st == FH_OK) st = device_alloc(&vh, sizeof(int32_t));
+    b->d_head = static_cast<int32_t*>(vh);
+    if (st != FH_OK) {
+      batch_free(b);
+      return st;
+    }
   }
   if (hipMemcpy(b->d_maps, b->args.data(), sizeof(MapArgs) * m, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(b->d_queue, q.data(), sizeof(Unit) * q.size(), hipMemcpyHostToDevice) != hipSuccess ||
@@ -1172,6 +1188,7 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
     ok = hipStreamEndCapture(b->cap, &b->graph) == hipSuccess;
   }
   if (ok) ok = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess;
+  if (ok && fake_device_error("graph")) ok = false;  // test hook: as if instantiation had failed
   if (!ok) {
     batch_free(b);
     return FH_EDEVICE;

@@ -113,6 +113,17 @@ int lds_bytes_for_shape(int n_f, int rows, int cols, int a_lds, int threads, int
 void split_units(const Plan& p, int32_t mi, double target, std::vector<Unit>& units, std::vector<double>& cost,
                  std::vector<int4>& clears);
 
+// Device allocation of the library (hipMalloc); FH_ENOMEM on out-of-memory,
+// FH_EDEVICE on other failures.  Test hook: with the environment variable
+// FH_FAKE_OOM set every such allocation fails with FH_ENOMEM.
+fh_status device_alloc(void** p, size_t bytes);
+// Test hook: true when the environment variable FH_FAKE_DEVICE_ERROR names
+// `what` ("graph": graph instantiation of a batch fails).
+bool fake_device_error(const char* what);
+// Host checks of a peak list: row_ptr set, 0 <= n_peaks < 2^31, bin set when
+// n_peaks > 0 and 16-byte aligned (the windowed tiles read it 16 bytes at a time).
+fh_status check_peaks(const fh_peaks* pk);
+
 // implemented in fh_hough.hip
 fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStream_t s,
                        const SelArgs* sel = nullptr);

@@ -266,18 +266,40 @@ static void debug_report(const char* what, hipError_t e) {
   if (std::getenv("FH_DEBUG")) std::fprintf(stderr, "fh: %s failed: %s\n", what, hipGetErrorString(e));
 }
 
+fh_status device_alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (std::getenv("FH_FAKE_OOM")) return FH_ENOMEM;
+  const hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+  if (e != hipSuccess) {
+    debug_report("hipMalloc", e);
+    *p = nullptr;
+    return e == hipErrorOutOfMemory ? FH_ENOMEM : FH_EDEVICE;
+  }
+  return FH_OK;
+}
+
+bool fake_device_error(const char* what) {
+  const char* e = std::getenv("FH_FAKE_DEVICE_ERROR");
+  return e && std::strcmp(e, what) == 0;
+}
+
+fh_status check_peaks(const fh_peaks* pk) {
+  if (!pk || !pk->row_ptr) return FH_EINVAL;
+  if (pk->n_peaks < 0 || pk->n_peaks >= (1LL << 31)) return FH_EINVAL;
+  if (pk->n_peaks > 0 && !pk->bin) return FH_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(pk->bin) & 15) != 0) return FH_EINVAL;
+  return FH_OK;
+}
+
 template <typename T>
 static fh_status upload(T** dst, const T* src, size_t n) {
   if (n == 0) n = 1;
-  if (std::getenv("FH_FAKE_OOM")) return FH_ENOMEM;
-  hipError_t e = hipMalloc((void**)dst, n * sizeof(T));
-  if (e != hipSuccess) {
-    debug_report("hipMalloc", e);
-    *dst = nullptr;
-    return e == hipErrorOutOfMemory ? FH_ENOMEM : FH_EDEVICE;
-  }
+  void* v = nullptr;
+  const fh_status st = device_alloc(&v, n * sizeof(T));
+  *dst = static_cast<T*>(v);
+  if (st != FH_OK) return st;
   if (src) {
-    e = hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+    const hipError_t e = hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       debug_report("hipMemcpy", e);
       return FH_EDEVICE;
@@ -477,10 +499,10 @@ extern "C" void fh_plan_destroy(fh_plan_t h) {
   delete p;
 }
 
+extern "C" fh_status fh_peaks_validate(const fh_peaks* pk) { return check_peaks(pk); }
+
 extern "C" fh_status fh_hough(fh_plan_t h, const fh_peaks* pk, int32_t* map, void* stream) {
-  if (!h || !pk || !map || !pk->row_ptr) return FH_EINVAL;
-  if (pk->n_peaks < 0 || pk->n_peaks >= (1LL << 31)) return FH_EINVAL;
-  if (pk->n_peaks > 0 && !pk->bin) return FH_EINVAL;
+  if (!h || !map || check_peaks(pk) != FH_OK) return FH_EINVAL;
   const Plan& p = reinterpret_cast<Plan&>(*h);
   return launch_hough(p, *pk, map, (hipStream_t)stream);
 }

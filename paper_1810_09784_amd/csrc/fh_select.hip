@@ -336,11 +336,10 @@ static fh_status sel_scratch(Plan& p, const fh_select_opts& o, unsigned long lon
     if (p.dSel) (void)hipFree(p.dSel);
     p.dSel = nullptr;
     p.sel_words = 0;
-    const hipError_t e = hipMalloc((void**)&p.dSel, need * sizeof(unsigned long long));
-    if (e != hipSuccess) {
-      p.dSel = nullptr;
-      return e == hipErrorOutOfMemory ? FH_ENOMEM : FH_EDEVICE;
-    }
+    void* v = nullptr;
+    const fh_status st = device_alloc(&v, need * sizeof(unsigned long long));
+    if (st != FH_OK) return st;
+    p.dSel = static_cast<unsigned long long*>(v);
     p.sel_words = need;
   }
   *rows = p.dSel;
@@ -498,9 +497,7 @@ extern "C" fh_status fh_select_noalloc(fh_plan_t h, const int32_t* map, const fh
 
 extern "C" fh_status fh_hough_select(fh_plan_t h, const fh_peaks* pk, int32_t* map, const fh_select_opts* o,
                                      void* stream) {
-  if (!h || !pk || !map || !pk->row_ptr || !o) return FH_EINVAL;
-  if (pk->n_peaks < 0 || pk->n_peaks >= (1LL << 31)) return FH_EINVAL;
-  if (pk->n_peaks > 0 && !pk->bin) return FH_EINVAL;
+  if (!h || !map || !o || check_peaks(pk) != FH_OK) return FH_EINVAL;
   Plan& p = reinterpret_cast<Plan&>(*h);
   fh_select_opts r;
   fh_status st = check_opts(p, o, &r);
@@ -577,11 +574,10 @@ extern "C" fh_status fh_batch_select(fh_batch_t b, const fh_select_opts* o, fh_c
     if (b->d_sel) (void)hipFree(b->d_sel);
     b->d_sel = nullptr;
     b->sel_bytes = 0;
-    const hipError_t e = hipMalloc((void**)&b->d_sel, need);
-    if (e != hipSuccess) {
-      b->d_sel = nullptr;
-      return e == hipErrorOutOfMemory ? FH_ENOMEM : FH_EDEVICE;
-    }
+    void* v = nullptr;
+    const fh_status st = device_alloc(&v, need);
+    if (st != FH_OK) return st;
+    b->d_sel = static_cast<unsigned long long*>(v);
     b->sel_bytes = need;
   }
   SelMap* d_tab = reinterpret_cast<SelMap*>(b->d_sel);

@@ -91,6 +91,7 @@ SIGNATURES = {
                                   C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_void_p]),
     "fh_batch_propose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_void_p,
                                    C.c_void_p]),
+    "fh_peaks_validate": (C.c_int, [C.c_void_p]),
     "fh_select": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SelectOpts), C.c_void_p, C.c_int32,
                             C.POINTER(C.c_int32), C.c_void_p]),
     "fh_select_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SelectOpts), C.c_void_p, C.c_int32,

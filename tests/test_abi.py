@@ -79,3 +79,36 @@ def test_null_arguments():
     assert L.fh_batch_create(0, None, None, None, C.byref(h)) == fh.FH_EINVAL
     assert fh.status_str(fh.FH_ERANGE) == "size out of range"
     assert b"gfx950" in L.fh_version()
+
+
+def _peaks(row_ptr_addr, bin_addr, n):
+    return fh.Peaks(C.c_void_p(row_ptr_addr), C.c_void_p(bin_addr), n)
+
+
+def test_peaks_validated_on_host():
+    # fh_peaks_validate reads no memory: host addresses stand in for device ones
+    L = fh.lib()
+    buf = np.zeros(64, dtype=np.int32)
+    a = buf.ctypes.data
+    base = a + (-a) % 16  # a 16-byte aligned address inside the buffer
+    assert L.fh_peaks_validate(None) == fh.FH_EINVAL
+    assert L.fh_peaks_validate(C.byref(_peaks(base, base, 10))) == fh.FH_OK
+    assert L.fh_peaks_validate(C.byref(_peaks(base, base + 4, 10))) == fh.FH_EINVAL   # bin not 16-byte aligned
+    assert L.fh_peaks_validate(C.byref(_peaks(base, base + 8, 10))) == fh.FH_EINVAL
+    assert L.fh_peaks_validate(C.byref(_peaks(0, base, 10))) == fh.FH_EINVAL          # no row_ptr
+    assert L.fh_peaks_validate(C.byref(_peaks(base, 0, 10))) == fh.FH_EINVAL          # no bins for 10 peaks
+    assert L.fh_peaks_validate(C.byref(_peaks(base, 0, 0))) == fh.FH_OK               # an empty peakmap
+    assert L.fh_peaks_validate(C.byref(_peaks(base, base, -1))) == fh.FH_EINVAL
+    assert L.fh_peaks_validate(C.byref(_peaks(base, base, 2 ** 31))) == fh.FH_EINVAL
+    # fh_hough rejects the same before using its plan
+    assert L.fh_hough(None, C.byref(_peaks(base, base + 4, 10)), C.c_void_p(base), None) == fh.FH_EINVAL
+
+
+def test_fake_oom_fails_the_plan_before_any_device_memory(monkeypatch):
+    monkeypatch.setenv("FH_FAKE_OOM", "1")
+    k = np.ascontiguousarray([0.0, 1e-9], dtype=np.float64)
+    dp = C.POINTER(C.c_double)
+    d = fh.MapDesc(3.0, 2.0, 100.0, 150.0, 10, dp(), 2, k.ctypes.data_as(dp), 0.0, 0.0, 0)
+    h = C.c_void_p()
+    assert fh.lib().fh_plan(C.byref(d), None, C.byref(h)) == fh.FH_ENOMEM
+    assert not h.value
