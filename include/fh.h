@@ -382,16 +382,22 @@ fh_status fh_coincide(int32_t n_seg, int32_t na, const int32_t* a_off, const fh_
  * binary64: mu = S/N, var = S2/N - mu^2, sigma = sqrt(var); sigma = 0 gives
  * CR = NaN).  Peaks with a bin outside [0, n_f) are skipped.  The plan gives
  * n, tfft, f_min and the times T_i.  Each FFT's window of bins is found by
- * binary search, so a non-ascending FFT leaves its contribution unspecified. */
+ * binary search, so a non-ascending FFT leaves its contribution unspecified.
+ * pow is the host C library's: the device evaluates the drift with its own
+ * pow and, for a candidate where some (f(T_i) - f_min) * tfft lies within
+ * rounding distance of an integer, the host evaluates that candidate's drift
+ * table and the candidate is projected again (host_drift = 1). */
 typedef struct {
-  int32_t y, pad;            /* peaks in bin b_0 after the move */
+  int32_t y;                 /* peaks in bin b_0 after the move */
+  int32_t host_drift;        /* 1: this candidate's drift came from the host's table */
   double mu, sigma, cr;
 } fh_projection;
 
 /* n_cand candidates, f0 and k DEVICE double [n_cand]; hist DEVICE int32
  * [n_cand][2w+1] (bin b_0 + d at index w + d) written; out HOST [n_cand].
- * 1 <= w <= 4096, 0 <= guard < w.  Synchronises `stream`.  Errors:
- * FH_EINVAL, FH_EDEVICE. */
+ * 1 <= w <= 4096, 0 <= guard < w.  The plan's projection scratch (4 (n_cand
+ * + n_fft) bytes) is allocated on first use or growth.  Synchronises
+ * `stream`.  Errors: FH_EINVAL, FH_ENOMEM, FH_EDEVICE. */
 fh_status fh_project(fh_plan_t plan, const fh_peaks* peaks, int32_t n_cand, const double* f0, const double* k,
                      int32_t w, int32_t guard, int32_t* hist, fh_projection* out, void* stream);
 

@@ -95,6 +95,8 @@ struct Plan {
   hipEvent_t ev_sel = nullptr;        // recorded after that copy
   int32_t sel_pending = 0;            // results of an fh_hough_select not yet fetched
   fh_select_opts sel_opts{};          // its options (col_hi resolved)
+  int32_t* dProj = nullptr;           // fh_project scratch: candidate flags, one drift table
+  size_t proj_words = 0;
   int32_t grid = 0;  // persistent work-groups of a single-map launch
   int device = 0;
   int n_cu = 256;

@@ -248,6 +248,9 @@ static void free_dev(Plan& p) {
   if (p.dSel) (void)hipFree(p.dSel);
   p.dSel = nullptr;
   p.sel_words = 0;
+  if (p.dProj) (void)hipFree(p.dProj);
+  p.dProj = nullptr;
+  p.proj_words = 0;
   if (p.hSq) (void)hipHostFree(p.hSq);
   p.hSq = nullptr;
   p.hsq_words = 0;

@@ -58,7 +58,8 @@ class Candidate(C.Structure):
 
 
 class Projection(C.Structure):
-    _fields_ = [("y", C.c_int32), ("pad", C.c_int32), ("mu", C.c_double), ("sigma", C.c_double), ("cr", C.c_double)]
+    _fields_ = [("y", C.c_int32), ("host_drift", C.c_int32), ("mu", C.c_double), ("sigma", C.c_double),
+                ("cr", C.c_double)]
 
 
 class PlanInfo(C.Structure):
@@ -342,7 +343,8 @@ def fh_project(plan: Plan, row_ptr, bin_, f0, k, w: int = 40, guard: int = 2, st
     _check(lib().fh_project(plan.handle, C.byref(pk), n, C.c_void_p(_ptr(f0)), C.c_void_p(_ptr(k)), int(w),
                             int(guard), C.c_void_p(_ptr(hist)), out,
                             _stream(stream)), "fh_project")
-    return hist[:n], [{"y": out[i].y, "mu": out[i].mu, "sigma": out[i].sigma, "cr": out[i].cr} for i in range(n)]
+    return hist[:n], [{"y": out[i].y, "mu": out[i].mu, "sigma": out[i].sigma, "cr": out[i].cr,
+                       "host_drift": out[i].host_drift} for i in range(n)]
 
 
 def fh_coincide(a_off, a, b_off, b, max_d: float = 3.0, nm1=None, dt=None, cap: Optional[int] = None,

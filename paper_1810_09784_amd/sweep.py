@@ -57,10 +57,14 @@ class Sweep:
 
     def __init__(self, dev, seed: int = 5, n_values=N_VALUES, tffts=TFFTS, n_bands: int = 30, t_obs: float = T_OBS,
                  n_k: int = N_K, n_inj: int = 200, amp_lo: float = 1.0, amp_hi: float = 4.0, log=None,
-                 k_layout: str = "uniform"):
+                 k_layout: str = "uniform", groups=None):
+        """groups: optional set of (band index, T_FFT index) to build, the others
+        are left out (the injections are drawn for the whole sweep either way,
+        so a group is built the same alone or with the rest)."""
         import torch
         from . import fh
         self.dev = dev
+        self.seed = seed
         rng = np.random.default_rng(seed)
         self.bands = band_edges(n_bands)
         self.n_values, self.tffts = tuple(n_values), tuple(tffts)
@@ -80,13 +84,17 @@ class Sweep:
             k = float(ks[row])
             f0 = float(rng.uniform(lo + 4.0, hi - 4.0))
             inj.append((b, ti, ni, f0, k, float(rng.uniform(amp_lo, amp_hi)), row))
-        self.injections = inj
+        built = (lambda b, ti: True) if groups is None else (lambda b, ti: (b, ti) in groups)
+        self.injections = [x for x in inj if built(x[0], x[1])]
         self.peakmaps = {}   # (band, ti) -> (row_ptr, bin)
         self.maps = []       # dicts: band, ti, ni, plan, hmap, peaks key, U
+        self._index = {}     # (band, ti, ni) -> position in maps
         self.U = 0
         t = time.perf_counter()
         for b, (lo, hi) in enumerate(self.bands):
             for ti, tfft in enumerate(self.tffts):
+                if not built(b, ti):
+                    continue
                 n_fft = int(t_obs / tfft)
                 injs = [S.Injection(f0=f0, tau=1.0 / (k * (self.n_values[ni] - 1) * f0 ** (self.n_values[ni] - 1)),
                                     n=self.n_values[ni], amp=amp)
@@ -100,6 +108,7 @@ class Sweep:
                     kk = map_k(k_layout, n, tfft, lo, hi, n_k)
                     plan = fh.Plan(n, tfft, lo, hi, n_fft, kk)
                     hmap = torch.empty((plan.n_k, plan.n_x0), dtype=torch.int32, device=dev)
+                    self._index[(b, ti, ni)] = len(self.maps)
                     self.maps.append({"band": b, "ti": ti, "ni": ni, "n": n, "tfft": tfft, "f_min": lo, "f_max": hi,
                                       "n_fft": n_fft, "k": kk, "plan": plan, "hmap": hmap, "P": P})
                     self.U += P * len(kk)
@@ -114,7 +123,7 @@ class Sweep:
                               [m["hmap"] for m in self.maps])
 
     def map_index(self, b, ti, ni):
-        return (b * len(self.tffts) + ti) * len(self.n_values) + ni
+        return self._index[(b, ti, ni)]
 
     def destroy(self):
         self.batch.destroy()
@@ -302,6 +311,95 @@ def evaluate_at_fap(dev, net, faps, n_noise_sweeps: int, seed: int, sw: Optional
                                           "eff_plain": float(np.mean(best[sel, 0] >= thr_p)),
                                           "eff_learned": float(np.mean(best[sel, 1] >= thr_l))})
     return out
+
+
+class Checkpoint:
+    """Per-map results of a sweep in a JSON-lines file, one record per map keyed
+    by (n, T_FFT, f_min, f_max, seed).  Records are appended and flushed to disk
+    one at a time; a last line cut short by a crash is dropped on reload."""
+
+    def __init__(self, path: str):
+        import json
+        import os
+        self.path = path
+        self.done = {}
+        good = 0
+        if os.path.exists(path):
+            with open(path, "rb") as f:
+                data = f.read()
+            at = 0
+            for line in data.split(b"\n")[:-1]:  # the text after the last newline is incomplete
+                at += len(line) + 1
+                try:
+                    rec = json.loads(line)
+                except ValueError:
+                    break
+                if not isinstance(rec, dict) or "key" not in rec:
+                    break
+                self.done[self.key(*rec["key"])] = rec
+                good = at
+            if good != len(data):
+                with open(path, "r+b") as f:
+                    f.truncate(good)
+
+    @staticmethod
+    def key(n, tfft, f_min, f_max, seed):
+        return (float(n), float(tfft), float(f_min), float(f_max), int(seed))
+
+    def write(self, rec: dict):
+        import json
+        import os
+        with open(self.path, "a") as f:
+            f.write(json.dumps(rec) + "\n")
+            f.flush()
+            os.fsync(f.fileno())
+        self.done[self.key(*rec["key"])] = rec
+
+
+def run_resumable(dev, path: str, sq=(8, 8), min_dk: int = 3, cr_thr: float = 4.0, after_group=None, log=None,
+                  **kw) -> int:
+    """The sweep one (band, T_FFT) group of maps at a time (one batched launch
+    and one batched selection per group), each map's result appended to the
+    checkpoint file `path` as soon as its group is done: its candidates with
+    CR >= cr_thr, the map's CRC-32 and total count, and its bad-peak count.
+    Maps already in the file are skipped, so a run that stopped part-way
+    continues where it stopped.  after_group(b, ti) is called after each group
+    that was computed.  Returns the number of maps computed by this call."""
+    import zlib
+    import torch
+    from . import fh
+    ck = Checkpoint(path)
+    seed = kw.get("seed", 5)
+    bands = band_edges(kw.get("n_bands", 30))
+    tffts = tuple(kw.get("tffts", TFFTS))
+    n_values = tuple(kw.get("n_values", N_VALUES))
+    computed = 0
+    for b, (lo, hi) in enumerate(bands):
+        for ti, tfft in enumerate(tffts):
+            keys = [Checkpoint.key(n, tfft, lo, hi, seed) for n in n_values]
+            if all(k in ck.done for k in keys):
+                continue
+            sw = Sweep(dev, groups={(b, ti)}, **kw)
+            sw.batch.launch()
+            torch.cuda.synchronize()
+            cands = sw.batch.select(sq[0], sq[1], min_dk, cr_thr=cr_thr, as_dicts=False)
+            for m, cl in zip(sw.maps, cands):
+                key = Checkpoint.key(m["n"], m["tfft"], m["f_min"], m["f_max"], seed)
+                if key in ck.done:
+                    continue
+                h = m["hmap"].cpu().numpy()
+                ck.write({"key": list(key), "n_k": int(h.shape[0]), "n_x0": int(h.shape[1]),
+                          "map_crc32": int(zlib.crc32(h.tobytes())), "map_sum": int(h.sum(dtype=np.int64)),
+                          "bad_peaks": int(fh.fh_device_errors(m["plan"])),
+                          "candidates": [[int(c["row"]), int(c["col"]), int(c["count"]), int(c["second"]),
+                                          float(c["cr"])] for c in cl]})
+                computed += 1
+            sw.destroy()
+            if log:
+                log(f"sweep group band {b} T_FFT {tfft}: {len(sw.maps)} maps done")
+            if after_group:
+                after_group(b, ti)
+    return computed
 
 
 def main():

@@ -98,3 +98,35 @@ def test_reduced_sweep_at_fixed_fap(dev, oracle):
     for a, b in zip(res[:-1], res[1:]):
         assert b["thr_plain"] >= a["thr_plain"] and b["thr_learned"] >= a["thr_learned"]
         assert b["eff_plain"] <= a["eff_plain"] and b["eff_learned"] <= a["eff_learned"]
+
+
+def test_resumable_sweep_continues_after_a_crash(dev, tmp_path):
+    # a reduced sweep run through the per-map checkpoint, interrupted after its
+    # first group of maps (and with a torn record at the end of the file), then
+    # resumed: the result equals an uninterrupted run, and the maps done before
+    # the crash are not computed again
+    from paper_1810_09784_amd import sweep
+    kw = dict(n_values=(2.0, 4.5), tffts=(2.0, 8.0), n_bands=2, t_obs=20000.0, n_k=48, n_inj=4, seed=17)
+    full = str(tmp_path / "full.jsonl")
+    assert sweep.run_resumable(dev, full, cr_thr=3.0, **kw) == 8
+
+    class Crash(Exception):
+        pass
+
+    def crash(b, ti):
+        raise Crash()
+
+    part = str(tmp_path / "part.jsonl")
+    try:
+        sweep.run_resumable(dev, part, cr_thr=3.0, after_group=crash, **kw)
+    except Crash:
+        pass
+    with open(part, "a") as f:
+        f.write('{"key": [4.5, 8.0')
+    assert sweep.run_resumable(dev, part, cr_thr=3.0, **kw) == 6  # the first group's 2 maps were done
+    a = sweep.Checkpoint(full).done
+    b = sweep.Checkpoint(part).done
+    assert a.keys() == b.keys() and len(a) == 8
+    for k in a:
+        assert a[k] == b[k], k
+    assert any(r["candidates"] for r in a.values())
