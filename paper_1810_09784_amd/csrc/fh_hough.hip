@@ -71,24 +71,60 @@ __device__ __forceinline__ double readlane_f64(double x, int l) {
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// One (peak, row) pair: the +1/-1 edges of its clipped interval in the tile.
-// Drow points at the tile row (its slot at index c1 - c0 absorbs right edges
-// outside the tile); an empty or invalid interval sends both edges to the
-// lane's own discard word, so the update needs no branch.
+// v_med3_i32: the middle of three values, here x clamped to [a, b] (a <= b).
+__device__ __forceinline__ int med3_i32(int x, int a, int b) {
+  int r;
+  asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(a), "v"(b));
+  return r;
+}
+
+// One (peak, row) pair: +1 at the first column of its clipped interval in the
+// tile and -1 one past the last.  Drow + c is column c of the tile row (its
+// slot at c1 absorbs right edges outside the tile).  The columns are
+// floor(u_lo) .. floor(u_hi); trunc (the conversion) equals floor for u >= 0,
+// and clamped to c0 >= 0 the two agree for u_lo too.  For u_hi only tiles at
+// column 0 can tell them apart: there an interval with u_hi < 0 lies left of
+// the map and is dropped (ZERO_COL).  An empty interval (or one moved off the
+// tile) makes no LDS access at all: the atomics are masked off.
+// The clamp bounds of edge_update in vector registers (v_med3_i32 reads at
+// most one scalar operand): c0, c1, c0 - 1, c1 - 1.  Copied once per tile by
+// an instruction the compiler cannot move into the pair loops.
+struct EdgeBounds {
+  int c0, c1, c0m, c1m;
+  __device__ __forceinline__ EdgeBounds(int a, int b) {
+    asm volatile("v_mov_b32 %0, %1" : "=v"(c0) : "s"(a));
+    asm volatile("v_mov_b32 %0, %1" : "=v"(c1) : "s"(b));
+    asm volatile("v_mov_b32 %0, %1" : "=v"(c0m) : "s"(a - 1));
+    asm volatile("v_mov_b32 %0, %1" : "=v"(c1m) : "s"(b - 1));
+  }
+};
+
 template <bool ZERO_COL>
-__device__ __forceinline__ void edge_update(int* Dcol, int* discard, double C, double T, double a_lo, double a_hi,
-                                            int c0, int c1, bool valid) {
+__device__ __forceinline__ void edge_update(int* Drow, double C, double T, double a_lo, double a_hi,
+                                            const EdgeBounds& e) {
   const double u_lo = __builtin_fma(-C, T, a_lo);
   const double u_hi = __builtin_fma(-C, T, a_hi);
-  // max(floor(u), c0) == max(trunc(u), c0) for c0 >= 0.  floor(u_hi) < 0 iff
-  // u_hi < 0; trunc differs from floor there only on (-1, 0), which matters
-  // only when c0 == 0 (for c0 >= 1 such an interval already has hi < lo).
-  const int lo = max(cvt_sat_i32(u_lo), c0);
-  const int hi = min(cvt_sat_i32(u_hi), c1 - 1);
-  const bool ok = valid && (!ZERO_COL || !is_negative(u_hi)) && lo <= hi;
-  // Dcol + c is column c of the tile row; the -1 lands one past Dcol[hi]
-  int* plo = ok ? Dcol + lo : discard;
-  int* phi = ok ? Dcol + hi : discard - 1;
+  const int lo = med3_i32(cvt_sat_i32(u_lo), e.c0, e.c1);
+  const int hi = med3_i32(cvt_sat_i32(u_hi), e.c0m, e.c1m);  // the -1 goes to hi + 1
+  if (lo <= hi && (!ZERO_COL || u_hi >= 0.0)) {
+    atomicAdd(Drow + lo, 1);
+    atomicAdd(Drow + hi + 1, -1);
+  }
+}
+
+// The same update without a branch: an empty interval sends its +1 and -1 to
+// the lane's own discard word (where they cancel), so every lane makes its two
+// LDS accesses (the windowed pair loop, where most slots hold a pair).
+template <bool ZERO_COL>
+__device__ __forceinline__ void edge_update_nb(int* Drow, int* discard, double C, double T, double a_lo, double a_hi,
+                                               const EdgeBounds& e) {
+  const double u_lo = __builtin_fma(-C, T, a_lo);
+  const double u_hi = __builtin_fma(-C, T, a_hi);
+  const int lo = med3_i32(cvt_sat_i32(u_lo), e.c0, e.c1);
+  const int hi = med3_i32(cvt_sat_i32(u_hi), e.c0m, e.c1m);
+  const bool ok = lo <= hi && (!ZERO_COL || u_hi >= 0.0);
+  int* plo = ok ? Drow + lo : discard;
+  int* phi = ok ? Drow + hi : discard - 1;  // the -1 lands one past phi
   atomicAdd(plo, 1);
   atomicAdd(phi + 1, -1);
 }
@@ -184,8 +220,20 @@ struct WaveScratch {
   double T[kWave];     // time of each FFT of the block
   int rb[kWave];       // rows that can reach the tile at that FFT
   int rp[kWave + 4];   // CSR offsets of the block (65 used)
+  int mark[kWave];     // per 64-peak chunk: FFT (in the block) starting at each position, else -1
 };
-static_assert(sizeof(WaveScratch) == 1040, "per-wave LDS scratch size is part of the LDS budget");
+static_assert(sizeof(WaveScratch) == kWaveScratchBytes, "per-wave LDS scratch size is part of the LDS budget");
+
+// Inclusive maximum over the lanes of a wavefront (DPP, as wave_incl_scan).
+__device__ __forceinline__ int wave_incl_max(int x) {
+  x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x111, 0xf, 0xf, false));  // row_shr:1
+  x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x112, 0xf, 0xf, false));  // row_shr:2
+  x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x114, 0xf, 0xf, false));  // row_shr:4
+  x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x118, 0xf, 0xf, false));  // row_shr:8
+  x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  x = max(x, __builtin_amdgcn_update_dpp(INT_MIN, x, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return x;
+}
 
 
 // Fused candidate selection.  The epilogue produces each tile row's final
@@ -397,11 +445,12 @@ constexpr int kWinQuads = 2;  // windowed mode: 16-byte bin groups per loop step
 // Shared state of one unit, set up by tile_body.
 struct TileCtx {
   const double* A_s;      // A table in LDS (n_f + 2 entries) when ALDS
+  const double* C_s;      // C of the tile's rows in LDS
   WaveScratch* wsc;       // per-wave scratch of the whole-FFT mode
   const int* ia_s;        // per tile row: FFT range [ia, ib) that can reach the tile
   const int* ib_s;
-  const int* flags;       // [0]: ib non-increasing over the rows, [1] [2]: union FFT range
-  int* discard;           // this lane's sink of empty intervals
+  int* flags;             // [0]: ib non-increasing over the rows, [1] [2]: union FFT range, [3]: blocks claimed
+  int* discard;           // this lane's sink of empty intervals (windowed mode)
   int* D;                 // differential tile, rows x pitch
   int rt, ct, r0, nrows, c0, c1, pitch, i_lo, i_hi, lane, wave;
 };
@@ -414,11 +463,12 @@ template <int THREADS, bool ALDS, int MODE, bool ZERO_COL>
 __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, const TileCtx& X) {
   constexpr int NW = THREADS / kWave;
   const double* A_s = X.A_s;
+  const double* C_s = X.C_s;
   const int* ia_s = X.ia_s;
   const int* ib_s = X.ib_s;
   int* discard = X.discard;
   int* D = X.D;
-  const int rt = X.rt, ct = X.ct, r0 = X.r0, nrows = X.nrows, c0 = X.c0, c1 = X.c1, pitch = X.pitch;
+  const int rt = X.rt, ct = X.ct, nrows = X.nrows, c0 = X.c0, c1 = X.c1, pitch = X.pitch;
   const int i_lo = X.i_lo, i_hi = X.i_hi, lane = X.lane, wave = X.wave;
   if (MODE == 0 ? M.mode == kModeWhole : MODE == kModeWhole) {
     // Waves take blocks of 64 FFTs; lanes take the blocks' peaks 64 at a time
@@ -428,13 +478,21 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
     const int i_start = uniform(count_bad ? i_lo : X.flags[1]);
     const int i_end = uniform(count_bad ? i_hi : max(X.flags[2], X.flags[1]));
     WaveScratch& S = X.wsc[wave];
-    // C of tile row `lane` in each lane (rows <= 64): the row loop broadcasts it
-    // with v_readlane instead of a memory load per row
-    const double C_lane = G.C[r0 + min(lane, nrows - 1)];
+    const EdgeBounds eb(c0, c1);
+    // C of the tile's rows through the scalar cache (uniform row index)
+    const __attribute__((address_space(4))) double* Cg = (const __attribute__((address_space(4))) double*)M.C + X.r0;
     int prev_last = INT_MIN;  // bin of the previous chunk's last peak (bad-peak count)
-    for (int f0 = i_start + wave * kWave; f0 < i_end; f0 += NW * kWave) {
+    int* claim = X.flags + 3;
+    for (;;) {
+      // waves claim blocks of 64 FFTs in order until the range is done, so
+      // that no wave idles while another still has several blocks to go
+      int bi = 0;
+      if (lane == 0) bi = atomicAdd(claim, 1);
+      const int f0 = i_start + kWave * uniform(__builtin_amdgcn_readlane(bi, 0));
+      if (f0 >= i_end) break;
       const int nb = min(kWave, i_end - f0);
       const int fi = f0 + min(lane, nb - 1);
+      // lane l < nb: start of FFT f0 + l; lanes >= nb: the block's end
       const int rp_l = min(max(G.row_ptr[f0 + min(lane, nb)], 0), M.n_peaks);
       const int rp_e = uniform(min(max(G.row_ptr[f0 + nb], 0), M.n_peaks));
       const double Tf = fft_time(M, G, fi);
@@ -447,25 +505,36 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
         }
         rb = u;
       }
+      // FFT l starts a run of peaks when it has any (the next FFT's start is larger)
+      int rp_n = __shfl_down(rp_l, 1);
+      if (lane == kWave - 1) rp_n = rp_e;
+      const bool starts = lane < nb && rp_n > rp_l;
       wave_sync_lds();
       S.rp[lane] = rp_l;
       if (lane == 0) S.rp[kWave] = rp_e;
       S.T[lane] = Tf;
       S.rb[lane] = lane < nb ? rb : 0;
+      S.mark[lane] = -1;
       wave_sync_lds();
       const int Pa = uniform(S.rp[0]);
       const int Pb = max(rp_e, Pa);
+      int u_carry = 0;  // FFT of the previous chunk's last peak
+      int j_next = Pa < Pb ? G.bin[min(Pa + lane, Pb - 1)] : 0;  // the next chunk's bins, loaded one chunk ahead
       for (int pc = Pa; pc < Pb; pc += kWave) {
         const int p = pc + lane;
         const bool pv = p < Pb;
         const int pcl = pv ? p : Pa;
-        const int j = G.bin[pcl];
-        // block FFT of the peak: last k < nb with rp[k] <= p
-        int u = 0, w = nb - 1;
-        while (u < w) {
-          const int mid = (u + w + 1) >> 1;
-          if (S.rp[mid] <= pcl) u = mid; else w = mid - 1;
-        }
+        const int j = j_next;
+        if (pc + kWave < Pb) j_next = G.bin[min(pc + kWave + lane, Pb - 1)];
+        // FFT of each peak: every FFT marks the chunk position of its first peak,
+        // and a running maximum over the lanes carries the marks forward
+        const int sft = rp_l - pc;
+        if (starts && sft >= 0 && sft < kWave) S.mark[sft] = lane;
+        wave_sync_lds();
+        const int mk = S.mark[lane];
+        S.mark[lane] = -1;  // each lane clears the slot it read (in order within the wave)
+        const int u = wave_incl_max(max(mk, u_carry));
+        u_carry = __builtin_amdgcn_readlane(u, 63);
         const double T = S.T[u];
         const bool jv = pv && (unsigned)j < (unsigned)M.n_f;
         if (count_bad) {
@@ -477,25 +546,35 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
           const bool first = pcl == S.rp[u];
           if (pv && (!jv || (!first && j <= jm))) atomicAdd(M.err, 1ull);
         }
-        // a bad bin reads the pad entry A[n_f + 1] = +huge: an empty interval
-        const int jc = (int)min((unsigned)j, (unsigned)M.n_f);
+        // invalid lanes and bad bins read the pad entry A[n_f + 1] = +huge: an
+        // interval right of every tile, which writes nothing
+        const int jc = jv ? j : M.n_f;
         const double a_hi = ALDS ? A_s[jc] : G.A[jc];
         const double a_lo = ALDS ? A_s[jc + 1] : G.A[jc + 1];
-        const int rbl = jv ? S.rb[u] : 0;
-        const int rmax = wave_max(rbl);
-        for (int r = 0; r < rmax; ++r) {
-          const double C = readlane_f64(C_lane, r);
-          edge_update<ZERO_COL>(D + r * pitch - c0, discard, C, T, a_lo, a_hi, c0, c1, pv && r < rbl);
+        // rows that can reach the tile: largest for the chunk's first FFT when
+        // the rows' FFT ranges nest, else the largest over the lanes
+        const int rmax = mono ? uniform(S.rb[uniform(u)]) : wave_max(S.rb[u]);
+        // eight rows per step, their C read with one scalar load (the table has
+        // kCPad entries of padding after the last row)
+        int* Drow = D - c0;
+        for (int r = 0; r < rmax; r += 8, Drow += 8 * pitch) {
+          double c[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) c[q] = Cg[r + q];
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (r + q < rmax) edge_update<ZERO_COL>(Drow + q * pitch, c[q], T, a_lo, a_hi, eb);
         }
       }
     }
   } else {
     // Per row: each lane owns one FFT, finds the peaks whose image can reach
     // the tile's columns and walks them eight at a time.
+    const EdgeBounds eb(c0, c1);
     for (int rl = 0; rl < nrows; ++rl) {
       const int ia = ia_s[rl], ib = ib_s[rl];
-      const double C = G.C[r0 + rl];
-      int* Dcol = D + rl * pitch - c0;
+      const double C = C_s[rl];
+      int* Drow = D + rl * pitch - c0;
       for (int qb = ia + wave * kWave; qb < ib; qb += NW * kWave) {
         const int i = qb + lane;
         const bool iv = i < ib;
@@ -541,18 +620,17 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
 #pragma unroll
           for (int h = 0; h < kWinQuads; ++h) {
             double alo[4], ahi[4];
-            bool vv[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {  // table reads of four peaks before their atomics
               const int q = g + 4 * h + e;
-              vv[e] = q >= pa && q < pe;
-              // a bad bin reads the pad entry A[n_f + 1] = +huge: an empty interval
-              const int jc = (int)min((unsigned)jj[4 * h + e], (unsigned)M.n_f);
+              // peaks outside the window and bad bins read the pad entry A[n_f + 1]
+              // = +huge: an interval right of every tile, which writes nothing
+              const int jc = (q >= pa && q < pe) ? (int)min((unsigned)jj[4 * h + e], (unsigned)M.n_f) : M.n_f;
               ahi[e] = ALDS ? A_s[jc] : G.A[jc];
               alo[e] = ALDS ? A_s[jc + 1] : G.A[jc + 1];
             }
 #pragma unroll
-            for (int e = 0; e < 4; ++e) edge_update<ZERO_COL>(Dcol, discard, C, T, alo[e], ahi[e], c0, c1, vv[e]);
+            for (int e = 0; e < 4; ++e) edge_update_nb<ZERO_COL>(Drow, discard, C, T, alo[e], ahi[e], eb);
           }
         }
       }
@@ -657,31 +735,33 @@ __device__ void tile_body(const MapArgs& M, int tile, int i_lo, int i_hi, bool a
     for (int j = tid; j <= M.n_f + 1; j += THREADS) A_s[j] = G.A[j];
   if (clean_at != d_at || clean < nrows * pitch)
     for (int x = tid; x < nrows * pitch; x += THREADS) D[x] = 0;
-  if (tid < nrows) {
-    const double C = G.C[r0 + tid];
-    C_s[tid] = C;
-    int a, b;
-    fft_range(M, G, C, c0, c1, i_lo, i_hi, &a, &b);
-    ia_s[tid] = a;
-    ib_s[tid] = b;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    int mono = 1, lo = i_hi, hi = i_lo;
-    for (int r = 0; r < nrows; ++r) {
-      if (r > 0) mono &= ib_s[r] <= ib_s[r - 1];
-      if (ia_s[r] < ib_s[r]) {
-        lo = min(lo, ia_s[r]);
-        hi = max(hi, ib_s[r]);
-      }
+  if (wave == 0) {
+    // the rows' FFT ranges (one lane per row, nrows <= 64), whether they nest
+    // (ib non-increasing over the rows) and their union, by wave reductions
+    int a = i_hi, b = i_lo, b_prev = INT_MAX;
+    if (lane < nrows) {
+      const double C = G.C[r0 + lane];
+      C_s[lane] = C;
+      fft_range(M, G, C, c0, c1, i_lo, i_hi, &a, &b);
+      ia_s[lane] = a;
+      ib_s[lane] = b;
     }
-    flags[0] = mono;
-    flags[1] = lo;
-    flags[2] = hi;
+    b_prev = __shfl_up(b, 1);
+    const bool breaks = lane > 0 && lane < nrows && b > b_prev;
+    const bool some = a < b;
+    const int lo = -wave_max(some ? -a : INT_MIN + 1);
+    const int hi = wave_max(some ? b : INT_MIN);
+    if (lane == 0) {
+      flags[0] = __builtin_amdgcn_ballot_w64(breaks) == 0;
+      flags[1] = lo > i_hi ? i_hi : lo;  // no row reaches the tile: an empty range
+      flags[2] = hi < i_lo ? i_lo : hi;
+      flags[3] = 0;  // blocks of FFTs claimed so far (whole-FFT mode)
+    }
   }
   __syncthreads();
 
-  const TileCtx X{A_s, wsc, ia_s, ib_s, flags, discard, D, rt, ct, r0, nrows, c0, c1, pitch, i_lo, i_hi, lane, wave};
+  const TileCtx X{A_s, C_s, wsc, ia_s, ib_s, flags, discard, D, rt, ct, r0, nrows, c0, c1, pitch, i_lo, i_hi, lane,
+                  wave};
   if (c0 == 0) tile_pairs<THREADS, ALDS, MODE, true>(M, G, X);
   else tile_pairs<THREADS, ALDS, MODE, false>(M, G, X);
   __syncthreads();

@@ -18,13 +18,15 @@ constexpr int kMaxJTable = 1 << 24;     // largest column->bin table of the wind
 constexpr int kProfileSamples = 128;    // FFT samples of a tile's cost profile
 constexpr int kUnitAtomic = 1 << 30;    // flag bit of a unit's map field: add into the map
 constexpr int kMaxSelectSegments = 256; // squares along x0 in candidate selection
+constexpr int kWaveScratchBytes = 1296; // per-wave LDS scratch of the whole-FFT pair loop
+constexpr int kCPad = 8;                // zero entries after the last row of the device C table
 
 enum Mode : int32_t { kModeAuto = 0, kModeWhole = 1, kModeWindowed = 2 };
 
 // Everything a tile of one map needs, by value (kernel argument or table entry).
 struct MapArgs {
   const double* A;         // [n_f + 2] column coordinate of each bin edge, then a pad +huge
-  const double* C;         // [n_k] column shift per second of each row
+  const double* C;         // [n_k + kCPad] column shift per second of each row, then zeros
   const double* T;         // [n_fft] time of each FFT
   const int32_t* J;        // [n_J] last bin edge j with A_j >= c (windowed mode)
   uint2* rank;             // [n_fft][n_words] (#peaks below word, bit mask) (windowed mode)

@@ -26,9 +26,9 @@ static int round_up(int x, int m) { return (x + m - 1) / m * m; }
 int lds_bytes_for_shape(int n_f, int rows, int cols, int a_lds, int threads, int* pitch_out, int wave_scratch) {
   int pitch = round_up(cols + 1, 4);
   if (pitch_out) *pitch_out = pitch;
-  // [A][C rows][per-wave scratch 1040 B][ia, ib rows][16 + 4 ints][64 discard ints][D rows x pitch, 16-aligned]
-  long long b = (long long)rows * pitch * 4 + (long long)rows * 8 + (long long)(wave_scratch ? threads / 64 : 0) * 1040 +
-                (long long)rows * 8 + 80 + 16 + 256 + 16;
+  // [A][C rows][per-wave scratch][ia, ib rows][16 + 4 ints][64 discard ints][D rows x pitch, 16-aligned]
+  long long b = (long long)rows * pitch * 4 + (long long)rows * 8 +
+                (long long)(wave_scratch ? threads / 64 : 0) * kWaveScratchBytes + (long long)rows * 8 + 80 + 256 + 16;
   if (a_lds) b += (long long)(n_f + 2) * 8;
   return b > (1LL << 30) ? (1 << 30) : (int)b;
 }
@@ -450,7 +450,12 @@ extern "C" fh_status fh_plan(const fh_map_desc* d, const fh_tile_cfg* cfg, fh_pl
     a_pad.push_back(1e300);
     st = upload(&p.dA, a_pad.data(), a_pad.size());
   }
-  if (st == FH_OK) st = upload(&p.dC, p.C.data(), p.C.size());
+  if (st == FH_OK) {
+    // the row loop of the whole-FFT tiles reads C eight rows at a time
+    std::vector<double> c_pad(p.C);
+    c_pad.resize(p.C.size() + kCPad, 0.0);
+    st = upload(&p.dC, c_pad.data(), c_pad.size());
+  }
   if (st == FH_OK) st = upload(&p.dT, p.T.data(), p.T.size());
   if (st == FH_OK && p.n_J > 0) st = upload(&p.dJ, p.J.data(), p.J.size());
   if (st == FH_OK && c.mode == kModeWindowed)
