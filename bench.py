@@ -310,14 +310,16 @@ def run_batched(fh, synth, tune, ceilings, dev, stream, K, W, check_oracle, plai
     out = {}
     t = time.perf_counter()
     specs = synth.cfg_batched()
-    # each path with its own best shapes: the batch with the library's shapes (they
-    # suit the shared persistent launch), the per-map launches with the shapes the
-    # autotuner found for each map alone (python -m paper_1810_09784_amd.tune)
-    plans, plans_t, peaks, maps, pms, Ub = [], [], [], [], [], 0
-    for s in specs:
-        p = synth.make_peakmap(s)
-        pms.append(p)
-        pl = fh.Plan.from_spec(s)
+    # each path with its own best shapes: the batch with those tuned for its shared
+    # persistent launch, the per-map launches with the shapes the autotuner found
+    # for each map alone (python -m paper_1810_09784_amd.tune)
+    plans, plans_t, peaks, maps, Ub = [], [], [], [], 0
+    pms = [synth.make_peakmap(s) for s in specs]
+    # the batch's shapes tuned for its graph launch as a whole (tune.autotune_batch),
+    # else the library's own
+    tiles_b = tune.lookup_batch(specs, [p.n_peaks for p in pms])
+    for i, (s, p) in enumerate(zip(specs, pms)):
+        pl = fh.Plan.from_spec(s, tile=tiles_b[i] if tiles_b else None)
         plans.append(pl)
         plans_t.append(fh.Plan.from_spec(s, tile=tune.lookup(s, p.n_peaks)))
         peaks.append((torch.from_numpy(p.row_ptr).to(dev), torch.from_numpy(p.bin).to(dev)))
@@ -334,6 +336,7 @@ def run_batched(fh, synth, tune, ceilings, dev, stream, K, W, check_oracle, plai
         batch.launch(stream)  # the maps checked below are the batch's
     log(f"batched graph {ms_b:.4f} ms, plain per-map {ms_p:.4f} ms")
     out.update({"workload": "48 uneven maps (n x T_FFT x 2 seeds, 64 Hz bands, 2 h - 3 d, 64-1024 k)",
+                "tiles": "autotuned for the batch's graph launch" if tiles_b else "the library's own shapes",
                 "plain": "fh_hough map by map, each with its autotuned tile shape",
                 "updates_per_launch": Ub, "ms_batched": round(ms_b, 5),
                 "updates_per_s_batched": Ub / (ms_b * 1e-3)})

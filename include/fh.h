@@ -300,7 +300,10 @@ typedef struct fh_batch_s* fh_batch_t;
 
 /* Build the work queue and the graph.  Host arrays of length m (>= 1) are read
  * during the call; the plans must outlive the batch; the peak and map device
- * buffers must stay valid while the batch is launched.  Synchronous. */
+ * buffers must stay valid while the batch is launched.  The persistent launch
+ * uses one work-group size: that of the plans' tile shapes when they all have
+ * the same one and read whole FFTs, else 512 threads (whole-FFT maps only) or
+ * 256 (mixed).  Synchronous. */
 fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh_peaks* peaks, int32_t* const* maps,
                           fh_batch_t* out);
 /* Enqueue one replay of the batch on `stream`. */

@@ -1142,7 +1142,7 @@ fh_status launch_hough(const Plan& p, const fh_peaks& pk, int32_t* map, hipStrea
 
 using namespace fh;
 
-constexpr int kBatchWholeThreads = 512;  // batches of whole-FFT maps (measured best of 256/512/1024)
+constexpr int kBatchWholeThreads = 512;  // batches of whole-FFT maps whose plans differ in work-group size
 
 static void batch_free(fh_batch_s* b) {
   if (!b) return;
@@ -1166,17 +1166,21 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
   int lds = 0, prep_lds = 0;
   double total = 0;
   bool any_windowed = false;
-  // all whole-FFT maps: a kernel compiled for that mode alone, with 512-thread
-  // work-groups; otherwise both modes with 256 threads
-  bool all_whole = true;
+  // all whole-FFT maps: a kernel compiled for that mode alone, with the
+  // work-group size the plans agree on (else 512 threads); otherwise both modes
+  // with 256 threads
+  bool all_whole = true, same_threads = true;
   for (int i = 0; i < m; ++i) {
     if (!plans[i]) {
       batch_free(b);
       return FH_EINVAL;
     }
-    all_whole &= reinterpret_cast<const fh_plan_s*>(plans[i])->p.tile.mode == kModeWhole;
+    const fh_tile_cfg& t = reinterpret_cast<const fh_plan_s*>(plans[i])->p.tile;
+    all_whole &= t.mode == kModeWhole;
+    same_threads &= t.threads == reinterpret_cast<const fh_plan_s*>(plans[0])->p.tile.threads;
   }
-  b->threads = all_whole ? kBatchWholeThreads : 256;
+  const int common = reinterpret_cast<const fh_plan_s*>(plans[0])->p.tile.threads;
+  b->threads = all_whole ? (same_threads ? common : kBatchWholeThreads) : 256;
   b->mode = all_whole ? (int)kModeWhole : 0;
   for (int i = 0; i < m; ++i) {
     if (!plans[i] || !maps[i] || check_peaks(&peaks[i]) != FH_OK) {
@@ -1243,8 +1247,13 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
     batch_free(b);
     return FH_EDEVICE;
   }
-  if (b->mode == kModeWhole) set_lds_attr<kBatchWholeThreads, true, kModeWhole>(lds);
-  else set_lds_attr<256, true, 0>(lds);
+  if (b->mode == kModeWhole) {
+    if (b->threads == 1024) set_lds_attr<1024, true, kModeWhole>(lds);
+    else if (b->threads == 512) set_lds_attr<512, true, kModeWhole>(lds);
+    else set_lds_attr<256, true, kModeWhole>(lds);
+  } else {
+    set_lds_attr<256, true, 0>(lds);
+  }
   // capture: prologue (queue head, error words, split tiles cleared), rank
   // structures of windowed maps, one persistent kernel
   if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) {
@@ -1259,9 +1268,15 @@ extern "C" fh_status fh_batch_create(int32_t m, const fh_plan_t* plans, const fh
                        none, (const MapArgs*)b->d_maps, m, (const int4*)b->d_clears, b->n_clears, b->d_head);
     if (any_windowed)
       hipLaunchKernelGGL(k_prepare_batch, dim3(2048), dim3(kPrepWaves * 64), prep_lds, b->cap, b->d_maps, m);
-    if (b->mode == kModeWhole)
-      hipLaunchKernelGGL((k_queue<kBatchWholeThreads, true, kModeWhole>), dim3(b->grid), dim3(kBatchWholeThreads), lds,
-                         b->cap, none, (const MapArgs*)b->d_maps, (const Unit*)b->d_queue, b->n_queue, b->d_head);
+    if (b->mode == kModeWhole && b->threads == 1024)
+      hipLaunchKernelGGL((k_queue<1024, true, kModeWhole>), dim3(b->grid), dim3(1024), lds, b->cap, none,
+                         (const MapArgs*)b->d_maps, (const Unit*)b->d_queue, b->n_queue, b->d_head);
+    else if (b->mode == kModeWhole && b->threads == 512)
+      hipLaunchKernelGGL((k_queue<512, true, kModeWhole>), dim3(b->grid), dim3(512), lds, b->cap, none,
+                         (const MapArgs*)b->d_maps, (const Unit*)b->d_queue, b->n_queue, b->d_head);
+    else if (b->mode == kModeWhole)
+      hipLaunchKernelGGL((k_queue<256, true, kModeWhole>), dim3(b->grid), dim3(256), lds, b->cap, none,
+                         (const MapArgs*)b->d_maps, (const Unit*)b->d_queue, b->n_queue, b->d_head);
     else
       hipLaunchKernelGGL((k_queue<256, true, 0>), dim3(b->grid), dim3(256), lds, b->cap, none,
                          (const MapArgs*)b->d_maps, (const Unit*)b->d_queue, b->n_queue, b->d_head);

@@ -139,21 +139,123 @@ def autotune(spec, pm, dev, reps: int = 10, save: bool = True, verbose: bool = F
     return entry
 
 
+# ------------------------------------------------------------- batches --
+# A batch shares one persistent launch: one work-group size for every map, and
+# each map's rows per tile decide how much LDS its tiles take, hence how many
+# work-groups share a CU.  The batch is tuned as a whole: candidates are
+# (work-group size, LDS budget of a tile's differential rows, time splits),
+# each map's whole-FFT tile derived from them, and the objective is the time
+# of the batch's graph launch.
+
+BATCH_THREADS = (256, 512, 1024)
+BATCH_TILE_KB = (12, 16, 20, 24, 28, 32, 40)
+BATCH_TSPLIT = (16, 64)
+
+
+def batch_key(specs, peak_counts) -> str:
+    import hashlib
+    h = hashlib.sha256("|".join(key(s, int(p)) for s, p in zip(specs, peak_counts)).encode()).hexdigest()
+    return f"batch{len(specs)}_{h[:16]}"
+
+
+def batch_tile(n_x0: int, n_k: int, threads: int, tile_kb: int, tsplit: int) -> dict:
+    """A whole-FFT tile over all columns with as many rows (a power of two, at
+    most 64 and n_k) as fit tile_kb KB of differential rows."""
+    cols = min(n_x0, 8192)
+    pitch = (cols + 1 + 3) // 4 * 4
+    rows = max(1, min(64, tile_kb * 1024 // (pitch * 4)))
+    rows = 1 << (rows.bit_length() - 1)
+    return dict(mode=1, rows=min(rows, n_k), cols=cols, threads=threads, tsplit=tsplit)
+
+
+def batch_candidates():
+    return [None] + [dict(threads=t, tile_kb=kb, tsplit=ts) for t in BATCH_THREADS for kb in BATCH_TILE_KB
+                     for ts in BATCH_TSPLIT]
+
+
+def lookup_batch(specs, peak_counts) -> Optional[List[dict]]:
+    e = _load().get(batch_key(specs, peak_counts))
+    return [dict(t) for t in e["tiles"]] if e else None
+
+
+def autotune_batch(specs, pms, dev, reps: int = 10, save: bool = True, verbose: bool = False,
+                   candidates=None) -> dict:
+    """Time the batch's graph launch for every candidate (None: the library's
+    own shapes); every candidate must produce the same maps.  Maps that the
+    library would read in windowed mode keep its own shape."""
+    import torch
+    from . import fh
+    peaks = [(torch.from_numpy(p.row_ptr).to(dev), torch.from_numpy(p.bin).to(dev)) for p in pms]
+    auto = [fh.Plan.from_spec(s) for s in specs]
+    geo = [(p.n_x0, p.n_k, p.tile["mode"]) for p in auto]
+    for p in auto:
+        p.destroy()
+    maps = [torch.empty((k, x), dtype=torch.int32, device=dev) for x, k, _ in geo]
+    ref, best, n = None, None, 0
+    for cand in (candidates if candidates is not None else batch_candidates()):
+        tiles = [None if cand is None or mode != 1 else batch_tile(x, k, cand["threads"], cand["tile_kb"],
+                                                                   cand["tsplit"]) for x, k, mode in geo]
+        try:
+            plans = [fh.Plan.from_spec(s, tile=t) for s, t in zip(specs, tiles)]
+        except fh.FHError:
+            continue
+        b = fh.Batch(plans, peaks, maps)
+        for _ in range(2):
+            b.launch()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            b.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        got = [m.clone() for m in maps]
+        if ref is None:
+            ref = got
+        elif not all(torch.equal(a, c) for a, c in zip(ref, got)):
+            raise RuntimeError(f"batch candidate {cand} gives different maps")
+        if verbose:
+            print(f"  {ms:8.4f} ms  {cand}", flush=True)
+        n += 1
+        if best is None or ms < best[0]:
+            best = (ms, cand, [p.tile for p in plans])
+        b.destroy()
+        for p in plans:
+            p.destroy()
+    entry = {"tiles": best[2], "params": best[1], "ms": best[0], "n_candidates": n, "timed": "batch graph launch"}
+    if save:
+        c = _load()
+        c[batch_key(specs, [p.n_peaks for p in pms])] = entry
+        with open(CACHE_OUT, "w") as f:
+            json.dump(c, f, indent=1, sort_keys=True)
+    return entry
+
+
 def main():
-    """Tune the benchmark's workloads and write the cache: the large map for
-    its timed step (fh_hough_select with 5 x 5 squares, two plans on two
-    streams), the small map and the 48 batched maps for one launch at a time
-    (their shapes serve per-map launches; a batch runs the library's own
-    shapes, which suit its shared persistent launch better)."""
+    """Tune the benchmark's workloads and write the cache: the 48 batched maps
+    as one batch (graph launch), the large map for its timed step
+    (fh_hough_select with 5 x 5 squares, two plans on two streams), the small
+    map and the 48 batched maps each for one launch at a time (their shapes
+    serve per-map launches)."""
     import argparse
     import time
     import torch
     from . import synth
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=5)
-    ap.add_argument("--only", choices=("large", "small", "batched"), default=None)
+    ap.add_argument("--only", choices=("large", "small", "batched", "batch"), default=None)
     a = ap.parse_args()
     dev = torch.device("cuda:0")
+    if a.only in (None, "batch"):  # the 48 maps as one batch
+        specs = synth.cfg_batched()
+        pms = [synth.make_peakmap(s) for s in specs]
+        t = time.time()
+        e = autotune_batch(specs, pms, dev, reps=max(a.reps, 10), verbose=True)
+        print(f"batch of {len(specs)}: {e['params']} {e['ms']:.4f} ms of {e['n_candidates']} candidates, "
+              f"{time.time() - t:.1f} s", flush=True)
+        if a.only == "batch":
+            return
     work = [("large", synth.cfg_single_large(), 2, (5, 5, 3)), ("small", synth.cfg_single_small(), 1, None)]
     work += [("batched", s, 1, None) for s in synth.cfg_batched()]
     for name, spec, streams, sel in work:
