@@ -324,6 +324,29 @@ void fh_batch_destroy(fh_batch_t batch);
 fh_status fh_batch_select(fh_batch_t batch, const fh_select_opts* opts, fh_candidate* out, int32_t cap,
                           int32_t* counts, int32_t* n_out, void* stream);
 
+/* The selection re-checking given 64 x 64 tiles only (the tiles a proposer
+ * such as fh_propose picked): tile t = a * ceil(n_x0/64) + b is the rectangle
+ * rows 64a .. min(64a + 64, n_k) - 1, columns 64b .. min(64b + 64, n_x0) - 1
+ * (fh_propose's numbering), intersected with the analysed columns
+ * [col_lo, col_hi).  Each rectangle is selected on its own, as fh_select does a
+ * whole map: sq_k x sq_x0 squares over the rectangle, their statistics (mu,
+ * sigma, CR) from the rectangle's cells alone.  Candidates carry map rows and
+ * columns; `square` numbers the squares within their tile.  Only the listed
+ * tiles are read.  fh_select_tiles: n_tiles tile indices (HOST) of one map;
+ * fh_batch_select_tiles: n_req (map index, tile index) pairs (HOST int32
+ * [n_req][2]) over the maps of a batch (as written by its last launch).
+ * Candidates go to `out` (HOST) request after request, at most cap in all;
+ * counts[i] (HOST) gets request i's number with CR >= cr_thr (0 for a tile
+ * outside the analysed columns) and *n_out their sum.  The scratch is the
+ * plan's selection scratch, or the batch's; synchronises `stream`.  Errors:
+ * FH_EINVAL (a tile index outside the map, sq_k above a rectangle's rows or
+ * sq_x0 above its columns or 256), FH_ERANGE, FH_ENOMEM, FH_EDEVICE. */
+fh_status fh_select_tiles(fh_plan_t plan, const int32_t* map, const fh_select_opts* opts, int32_t n_tiles,
+                          const int32_t* tiles, fh_candidate* out, int32_t cap, int32_t* counts, int32_t* n_out,
+                          void* stream);
+fh_status fh_batch_select_tiles(fh_batch_t batch, const fh_select_opts* opts, int32_t n_req, const int32_t* req,
+                                fh_candidate* out, int32_t cap, int32_t* counts, int32_t* n_out, void* stream);
+
 /* fh_propose on every map of the batch (as written by its last launch) with
  * one network: row statistics of all maps in one launch, then the tiles of
  * all maps in the network's batches (tiles of several maps share a forward

@@ -351,14 +351,14 @@ static fh_status sel_scratch(Plan& p, const fh_select_opts& o, unsigned long lon
 // s0 first), and their candidates: the first ones up to cap go to out,
 // *total counts all of them.
 static void emit_squares(const Plan& p, const fh_select_opts& o, const unsigned long long* sq, int s0, int s1,
-                         fh_candidate* out, int32_t cap, int32_t* total_io) {
-  const int n_k = p.desc.n_k, sq_k = o.sq_k, sq_x0 = o.sq_x0;
+                         fh_candidate* out, int32_t cap, int32_t* total_io, int n_rows = -1, int row_off = 0) {
+  const int n_k = n_rows >= 0 ? n_rows : p.desc.n_k, sq_k = o.sq_k, sq_x0 = o.sq_x0;
   const int W = o.col_hi - o.col_lo;
   int32_t total = *total_io;
   const double inv1n = 1.0 / (1.0 - p.desc.n);
   auto emit = [&](unsigned long long key, unsigned long long col, int sqi, int second, double mu, double sigma) {
     const int y = (int)((unsigned)(key >> 32) ^ 0x80000000u);
-    const int r = (int)~(unsigned)(key & 0xffffffffu);
+    const int r = (int)~(unsigned)(key & 0xffffffffu) + row_off;
     const int c = (int)col;
     const double cr = ((double)y - mu) / sigma;
     if (!(cr >= o.cr_thr)) return;
@@ -547,6 +547,159 @@ extern "C" fh_status fh_select_results(fh_plan_t h, fh_candidate* out, int32_t c
   emit_candidates(p, p.sel_opts, p.hSq, out, cap, n_out);
   p.sel_pending = 0;
   return FH_OK;
+}
+
+// ------------------------------------------------- selection in tiles --
+// The selection of Sec. IV inside given 64 x 64 tiles of maps (the re-check
+// of the tiles a proposer picks): each tile's rectangle, intersected with the
+// analysed columns, is a small map of its own with sq_k x sq_x0 squares and
+// square-local statistics.  All rectangles go through the batched row pass
+// and square reduction in one launch each.
+namespace {
+
+struct Rect {
+  const Plan* p;
+  const int32_t* map;
+  int32_t r0, n_rows, c0, c1;
+};
+
+constexpr int kTile = 64;
+
+// The rectangle of tile t of a map of plan p, within the analysed columns of
+// o; false if it holds no analysed column.
+bool tile_rect(const Plan& p, const int32_t* map, const fh_select_opts& r, int t, Rect* out) {
+  const int tb = (p.n_x0 + kTile - 1) / kTile;
+  const int a = t / tb, b = t - a * tb;
+  const int r0 = a * kTile, c0 = std::max(b * kTile, r.col_lo), c1 = std::min(b * kTile + kTile, std::min(p.n_x0, r.col_hi));
+  if (r0 >= p.desc.n_k || c0 >= c1) return false;
+  *out = Rect{&p, map + (size_t)r0 * p.n_x0, r0, std::min(kTile, p.desc.n_k - r0), c0, c1};
+  return true;
+}
+
+fh_status select_rects(const std::vector<Rect>& rects, const std::vector<int32_t>& owner, int32_t n_owners,
+                       const fh_select_opts& o, unsigned long long** scratch, size_t* scratch_bytes, fh_candidate* out,
+                       int32_t cap, int32_t* counts, int32_t* n_out, hipStream_t s) {
+  const int m = (int)rects.size();
+  std::vector<SelMap> tab(m);
+  long long rows = 0, squares = 0;
+  for (int i = 0; i < m; ++i) {
+    const Rect& q = rects[i];
+    if (o.sq_k > q.n_rows || o.sq_x0 > std::min(q.c1 - q.c0, kMaxSelectSegments)) return FH_EINVAL;
+    tab[i] = SelMap{q.map, q.n_rows, q.p->n_x0, q.c0, q.c1, (int32_t)rows, (int32_t)squares};
+    rows += q.n_rows;
+    squares += (long long)o.sq_k * o.sq_x0;
+  }
+  for (int i = 0; i < n_owners; ++i) counts[i] = 0;
+  if (m == 0) {
+    *n_out = 0;
+    return FH_OK;
+  }
+  if (rows * o.sq_x0 >= (1LL << 31) || squares >= (1LL << 31)) return FH_ERANGE;
+  const size_t tab_bytes = ((sizeof(SelMap) * (size_t)m + 255) / 256) * 256;
+  const size_t row_words = (size_t)rows * o.sq_x0 * 3;
+  const size_t sq_words = (size_t)squares * kSqWords;
+  const size_t need = tab_bytes + 8 * (row_words + sq_words);
+  if (need > *scratch_bytes) {
+    if (*scratch) (void)hipFree(*scratch);
+    *scratch = nullptr;
+    *scratch_bytes = 0;
+    void* v = nullptr;
+    const fh_status st = device_alloc(&v, need);
+    if (st != FH_OK) return st;
+    *scratch = static_cast<unsigned long long*>(v);
+    *scratch_bytes = need;
+  }
+  SelMap* d_tab = reinterpret_cast<SelMap*>(*scratch);
+  unsigned long long* d_rows = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(*scratch) + tab_bytes);
+  unsigned long long* d_sq = d_rows + row_words;
+  if (hipMemcpyAsync(d_tab, tab.data(), sizeof(SelMap) * m, hipMemcpyHostToDevice, s) != hipSuccess)
+    return FH_EDEVICE;
+  const long long n_items = rows * o.sq_x0;
+  hipLaunchKernelGGL(k_select_rows_batch, dim3((unsigned)((n_items + kBatchSelWaves - 1) / kBatchSelWaves)),
+                     dim3(kBatchSelWaves * 64), 0, s, d_tab, m, n_items, o.sq_x0, d_rows);
+  hipLaunchKernelGGL(k_select_squares_batch, dim3((unsigned)squares), dim3(kSelThreads), 0, s, d_tab, m, o.sq_k,
+                     o.sq_x0, o.min_dk, d_rows, d_sq);
+  if (hipGetLastError() != hipSuccess) return FH_EDEVICE;
+  std::vector<unsigned long long> sq(sq_words);
+  if (hipMemcpyAsync(sq.data(), d_sq, sq_words * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return FH_EDEVICE;
+  int32_t total = 0, written = 0;
+  for (int i = 0; i < m; ++i) {
+    const Rect& q = rects[i];
+    fh_select_opts ro = o;
+    ro.col_lo = q.c0;
+    ro.col_hi = q.c1;
+    int32_t n = 0;
+    const int32_t room = cap - written;
+    emit_squares(*q.p, ro, sq.data() + (size_t)tab[i].sq0 * kSqWords, 0, o.sq_k * o.sq_x0, out ? out + written : nullptr,
+                 room, &n, q.n_rows, q.r0);
+    counts[owner[i]] += n;
+    written += std::min(n, room);
+    total += n;
+  }
+  *n_out = total;
+  return FH_OK;
+}
+
+}  // namespace
+
+extern "C" fh_status fh_select_tiles(fh_plan_t h, const int32_t* map, const fh_select_opts* o, int32_t n_tiles,
+                                     const int32_t* tiles, fh_candidate* out, int32_t cap, int32_t* counts,
+                                     int32_t* n_out, void* stream) {
+  if (!h || !map || !o || !n_out || n_tiles < 0 || (n_tiles > 0 && (!tiles || !counts)) || cap < 0 ||
+      (cap > 0 && !out))
+    return FH_EINVAL;
+  Plan& p = reinterpret_cast<Plan&>(*h);
+  fh_select_opts r = *o;
+  r.col_hi = o->col_hi > 0 ? o->col_hi : p.n_x0;
+  if (r.col_lo < 0 || r.col_hi > p.n_x0 || r.col_hi <= r.col_lo || r.sq_k < 1 || r.sq_x0 < 1) return FH_EINVAL;
+  const int n_tiles_map = ((p.desc.n_k + kTile - 1) / kTile) * ((p.n_x0 + kTile - 1) / kTile);
+  std::vector<Rect> rects;
+  std::vector<int32_t> owner;
+  for (int i = 0; i < n_tiles; ++i) {
+    if (tiles[i] < 0 || tiles[i] >= n_tiles_map) return FH_EINVAL;
+    Rect q;
+    if (tile_rect(p, map, r, tiles[i], &q)) {
+      rects.push_back(q);
+      owner.push_back(i);
+    }
+  }
+  // the plan's selection scratch, after a pending fused selection of the plan
+  if (p.sel_pending && hipEventSynchronize(p.ev_sel) != hipSuccess) return FH_EDEVICE;
+  size_t bytes = p.sel_words * 8;
+  unsigned long long* scr = p.dSel;
+  const fh_status st = select_rects(rects, owner, n_tiles, r, &scr, &bytes, out, cap, counts, n_out,
+                                    (hipStream_t)stream);
+  p.dSel = scr;
+  p.sel_words = bytes / 8;
+  return st;
+}
+
+extern "C" fh_status fh_batch_select_tiles(fh_batch_t b, const fh_select_opts* o, int32_t n_req, const int32_t* req,
+                                           fh_candidate* out, int32_t cap, int32_t* counts, int32_t* n_out,
+                                           void* stream) {
+  if (!b || !o || !n_out || n_req < 0 || (n_req > 0 && (!req || !counts)) || cap < 0 || (cap > 0 && !out))
+    return FH_EINVAL;
+  if (o->sq_k < 1 || o->sq_x0 < 1) return FH_EINVAL;
+  std::vector<Rect> rects;
+  std::vector<int32_t> owner;
+  for (int i = 0; i < n_req; ++i) {
+    const int mi = req[2 * i], t = req[2 * i + 1];
+    if (mi < 0 || mi >= b->m) return FH_EINVAL;
+    const Plan& p = *b->plans[mi];
+    fh_select_opts r = *o;
+    r.col_hi = o->col_hi > 0 ? std::min(o->col_hi, p.n_x0) : p.n_x0;
+    const int n_tiles_map = ((p.desc.n_k + kTile - 1) / kTile) * ((p.n_x0 + kTile - 1) / kTile);
+    if (t < 0 || t >= n_tiles_map || r.col_lo < 0) return FH_EINVAL;
+    Rect q;
+    if (r.col_lo < r.col_hi && tile_rect(p, b->maps[mi], r, t, &q)) {
+      rects.push_back(q);
+      owner.push_back(i);
+    }
+  }
+  return select_rects(rects, owner, n_req, *o, &b->d_sel, &b->sel_bytes, out, cap, counts, n_out,
+                      (hipStream_t)stream);
 }
 
 extern "C" fh_status fh_batch_select(fh_batch_t b, const fh_select_opts* o, fh_candidate* out, int32_t cap,

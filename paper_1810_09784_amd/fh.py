@@ -93,6 +93,10 @@ SIGNATURES = {
     "fh_batch_propose": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.c_void_p,
                                    C.c_void_p]),
     "fh_peaks_validate": (C.c_int, [C.c_void_p]),
+    "fh_select_tiles": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SelectOpts), C.c_int32, C.c_void_p, C.c_void_p,
+                                  C.c_int32, C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
+    "fh_batch_select_tiles": (C.c_int, [C.c_void_p, C.POINTER(SelectOpts), C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.c_int32, C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
     "fh_select": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SelectOpts), C.c_void_p, C.c_int32,
                             C.POINTER(C.c_int32), C.c_void_p]),
     "fh_select_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(SelectOpts), C.c_void_p, C.c_int32,
@@ -279,6 +283,27 @@ def fh_select(plan: Plan, hmap, sq_k: int, sq_x0: int, min_dk: int = 3, cr_thr: 
     return [buf[i].as_dict() for i in range(m)], int(n.value)
 
 
+def fh_select_tiles(plan: Plan, hmap, tiles: Sequence[int], sq_k: int, sq_x0: int, min_dk: int = 3,
+                    cr_thr: float = -1e300, col_lo: int = 0, col_hi: int = 0, cap: int = None, stream=None,
+                    as_dicts: bool = True):
+    """The selection inside the listed 64 x 64 tiles only, each with its own
+    squares and statistics: (candidates, per-tile counts, total)."""
+    import numpy as np
+    assert hmap.is_cuda and tuple(hmap.shape) == (plan.n_k, plan.n_x0) and hmap.is_contiguous()
+    t = np.ascontiguousarray(tiles, dtype=np.int32)
+    if cap is None:
+        cap = max(1, 2 * int(sq_k) * int(sq_x0) * len(t))
+    opts = SelectOpts(int(sq_k), int(sq_x0), int(min_dk), int(col_lo), int(col_hi), float(cr_thr))
+    buf = (Candidate * max(1, cap))()
+    counts = np.zeros(max(1, len(t)), dtype=np.int32)
+    n = C.c_int32()
+    _check(lib().fh_select_tiles(plan.handle, C.c_void_p(_ptr(hmap)), C.byref(opts), len(t), t.ctypes.data, buf,
+                                 int(cap), counts.ctypes.data, C.byref(n), _stream(stream)), "fh_select_tiles")
+    m = min(n.value, cap)
+    recs = np.ctypeslib.as_array(buf)[:m].copy() if not as_dicts else [buf[i].as_dict() for i in range(m)]
+    return recs, counts[:len(t)], int(n.value)
+
+
 def fh_select_noalloc(plan: Plan, hmap, sq_k: int, sq_x0: int, min_dk: int = 3, cr_thr: float = -1e300,
                       col_lo: int = 0, col_hi: int = 0, cap: int = None, stream=None, as_dicts: bool = True):
     """fh_select through the allocation-free entry point (fixed scratch array in
@@ -401,6 +426,22 @@ class Batch:
         h = C.c_void_p()
         _check(lib().fh_batch_create(m, self._plans, self._peaks, self._maps, C.byref(h)), "fh_batch_create")
         self.handle = h
+
+    def select_tiles(self, req, sq_k: int, sq_x0: int, min_dk: int = 3, cr_thr: float = -1e300, col_lo: int = 0,
+                     col_hi: int = 0, cap: int = None, stream=None):
+        """fh_batch_select_tiles: the selection inside the (map index, tile index)
+        pairs of req only: (candidate records, per-request counts, total)."""
+        r = np.ascontiguousarray(req, dtype=np.int32).reshape(-1, 2)
+        if cap is None:
+            cap = max(1, 2 * int(sq_k) * int(sq_x0) * r.shape[0])
+        opts = SelectOpts(int(sq_k), int(sq_x0), int(min_dk), int(col_lo), int(col_hi), float(cr_thr))
+        buf = (Candidate * max(1, cap))()
+        counts = np.zeros(max(1, r.shape[0]), dtype=np.int32)
+        n = C.c_int32()
+        _check(lib().fh_batch_select_tiles(self.handle, C.byref(opts), r.shape[0], r.ctypes.data, buf, int(cap),
+                                           counts.ctypes.data, C.byref(n), _stream(stream)), "fh_batch_select_tiles")
+        m = min(n.value, cap)
+        return np.ctypeslib.as_array(buf)[:m].copy(), counts[:r.shape[0]], int(n.value)
 
     def launch(self, stream=None):
         _check(lib().fh_batch_launch(self.handle, _stream(stream)), "fh_batch_launch")

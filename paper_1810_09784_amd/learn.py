@@ -17,11 +17,16 @@ Rows are normalised by their map row's mean and standard deviation.
 
 Evaluation.  A map is detected by a pipeline when one of its candidates has
 CR >= its threshold and lies within 3 bins (Euclidean, in x0 and k bins) of
-the injection's true cell.  Plain: the candidates of fh_select (4 x 6
-squares, second candidate 3 k rows away).  Learned: the same candidates
-restricted to the network's top tile(s).  Each pipeline's CR threshold is set
-on noise-only maps so that the fraction of noise maps with a candidate above
-it (the false-alarm probability per map) is the target FAP."""
+the injection's true cell.  Plain: the candidates of the selection over the
+whole map (4 x 6 squares, second candidate 3 k rows away).  Learned: the
+network scores the map's 12 tiles and the selection re-checks its top tile(s)
+alone (fh_batch_select_tiles: 2 x 1 squares of 32 x 64 cells inside the 64 x
+64 tile, statistics from the tile's cells), so it reads 1 of 12 tiles.  Each
+pipeline's CR threshold is set on noise-only maps so that the fraction of
+noise maps with a candidate above it (the false-alarm probability per map) is
+the target FAP.  Maps go through the library in batches (one persistent
+launch, one batched selection, one batched proposal and one batched re-check
+per batch)."""
 from __future__ import annotations
 
 import math
@@ -157,24 +162,38 @@ def train(net, X, y, epochs: int, lr: float, batch: int, seed: int, log=None) ->
     return hist
 
 
+TILE_SQ = (2, 1)  # squares of the re-check inside a 64 x 64 tile (32 x 64 cells, like the plain 32 x 54)
+
+
 def map_statistics(fac: MapFactory, net, inj: List[Tuple[float, float, float]], n_top: int = 1):
-    """Per map: (best CR of any plain candidate near the true cell or anywhere for
-    noise, same restricted to proposed tiles, proposed tiles, injection tile)."""
+    """Per map of one batch: (largest CR of the plain selection's candidates
+    within 3 bins of the injection's true cell, or of all candidates for a
+    noise map; the same for the re-check of the network's top tile(s))."""
+    import torch
     from . import fh
+    peaks = fac.draw(inj)
+    maps = [torch.empty((fac.plan.n_k, fac.plan.n_x0), dtype=torch.int32, device=fac.dev) for _ in inj]
+    b = fh.Batch([fac.plan] * len(inj), peaks, maps)
+    b.launch()
+    plain = b.select(SQ_K, SQ_X0, 3, as_dicts=False)
+    _, tops = fh.fh_batch_propose(net, b, [n_top] * len(inj))
+    req = [(i, t) for i, ts in enumerate(tops) for t in ts]
+    rc, counts, _ = b.select_tiles(req, TILE_SQ[0], TILE_SQ[1], 3)
+    b.destroy()
+    learned, at = [[] for _ in inj], 0
+    for (i, _), c in zip(req, counts):
+        learned[i].append(rc[at:at + c])
+        at += c
     out = []
-    maps = fac.hough(fac.draw(inj))
-    for (f0, k, a), H in zip(inj, maps):
-        cands, _ = fh.fh_select(fac.plan, H, SQ_K, SQ_X0, 3)
-        _, top = fh.fh_propose(net, fac.plan, H, n_top)
-        tops = set(top)
+    for q, (f0, k, a) in enumerate(inj):
+        lc = np.concatenate(learned[q]) if learned[q] else plain[q][:0]
         if a > 0:
             r, c = fac.true_cell(f0, k)
-            near = [x for x in cands if math.hypot(x["row"] - r, x["col"] - c) <= 3.0]
+            near = lambda x: np.hypot(x["row"] - r, x["col"] - c) <= 3.0
+            pc, lc = plain[q][near(plain[q])], lc[near(lc)]
         else:
-            near = cands
-        plain = max([x["cr"] for x in near], default=-math.inf)
-        learned = max([x["cr"] for x in near if tile_of(x["row"], x["col"]) in tops], default=-math.inf)
-        out.append((plain, learned))
+            pc = plain[q]
+        out.append((float(pc["cr"].max()) if len(pc) else -math.inf, float(lc["cr"].max()) if len(lc) else -math.inf))
     return out
 
 
@@ -187,7 +206,12 @@ def threshold_for_fap(noise_scores: np.ndarray, fap: float) -> float:
     return float(np.nextafter(s[k], np.inf)) if np.isfinite(s[k]) else -math.inf
 
 
-def evaluate(dev, net, amps, n_noise: int, n_per_amp: int, seed: int, fap: float, batch: int = 32, log=None):
+def evaluate(dev, net, amps, n_noise: int, n_per_amp: int, seed: int, fap: float, batch: int = 64, log=None):
+    """Both pipelines at one false-alarm probability per map: thresholds from
+    n_noise noise-only maps, then n_per_amp injected maps per amplitude.  The
+    two pipelines see the same maps, so their efficiencies are compared pair by
+    pair: se_diff is the standard error of eff_learned - eff_plain from the
+    maps where exactly one pipeline detects (McNemar)."""
     rng = np.random.default_rng(seed)
     fac = MapFactory(dev, seed + 7)
     noise = []
@@ -200,16 +224,23 @@ def evaluate(dev, net, amps, n_noise: int, n_per_amp: int, seed: int, fap: float
                               "fap_plain": float(np.mean(noise[:, 0] >= thr_plain)),
                               "fap_learned": float(np.mean(noise[:, 1] >= thr_learn)),
                               "tiles_touched_frac": 1.0 / 12.0, "curve": []}
+    if log:
+        log(f"{n_noise} noise maps: thresholds plain {thr_plain:.3f}, learned {thr_learn:.3f}")
     for a in amps:
         st = []
         for b0 in range(0, n_per_amp, batch):
             st += map_statistics(fac, net, [random_injection(rng, a) for _ in range(min(batch, n_per_amp - b0))])
         st = np.array(st)
-        e_p = float(np.mean(st[:, 0] >= thr_plain))
-        e_l = float(np.mean(st[:, 1] >= thr_learn))
-        res["curve"].append({"amp": a, "n": n_per_amp, "eff_plain": e_p, "eff_learned": e_l})
+        dp, dl = st[:, 0] >= thr_plain, st[:, 1] >= thr_learn
+        e_p, e_l = float(np.mean(dp)), float(np.mean(dl))
+        n = len(st)
+        p10, p01 = float(np.mean(dp & ~dl)), float(np.mean(dl & ~dp))
+        se_diff = math.sqrt(max(p10 + p01 - (p01 - p10) ** 2, 0.0) / n)
+        res["curve"].append({"amp": a, "n": n, "eff_plain": e_p, "eff_learned": e_l,
+                             "se_plain": math.sqrt(e_p * (1 - e_p) / n), "se_learned": math.sqrt(e_l * (1 - e_l) / n),
+                             "diff": e_l - e_p, "se_diff": se_diff})
         if log:
-            log(f"a = {a}: plain {e_p:.3f}, learned {e_l:.3f}")
+            log(f"a = {a}: plain {e_p:.4f}, learned {e_l:.4f} (difference {e_l - e_p:+.4f} +- {se_diff:.4f})")
     return res
 
 

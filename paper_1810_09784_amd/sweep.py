@@ -17,9 +17,10 @@ grids.
 One run: all maps in one batched persistent launch (captured graph), the
 plain selection (sq_k x sq_x0 squares, second candidate 3 rows away) on
 every map in one batched pass, the tile CNN's scores of every 64 x 64 tile
-and its top tiles, and the detection efficiency of the plain selection and
-of the selection restricted to the proposed tiles (a detection: a candidate
-with CR >= thr within 3 bins of the injection's true cell in its own map).  Candidates
+and its top tiles, the selection's re-check of those tiles alone (squares and
+statistics of the tile), and the detection efficiency of both pipelines (a
+detection: a candidate with CR >= thr within 3 bins of the injection's true
+cell in its own map).  Candidates
 farther than 10 bins from every injection of their map count as noise.
 """
 from __future__ import annotations
@@ -155,31 +156,45 @@ def time_plain(sw: Sweep):
     return e0.elapsed_time(e1)
 
 
-def evaluate(sw: Sweep, net=None, sq=(8, 8), top_frac: float = 0.1, thresholds=(4.0, 5.0, 6.0)):
-    """Selection on every map (and the CNN's proposals when net is given);
-    efficiencies of both pipelines at each CR threshold."""
+TILE_SQ = (2, 1)  # squares of the learned pipeline's re-check inside a 64 x 64 tile
+
+
+def _run_pipelines(sw: Sweep, net, sq, top_frac: float):
+    """Launch the batch and select on every map (plain pipeline); with a
+    network, score every map's tiles, take each map's top fraction and let the
+    selection re-check those tiles alone, with the tiles' own squares and
+    statistics (learned pipeline).  Returns (plain candidate records per map,
+    learned candidate records per map or None, seconds of the selection,
+    seconds of proposals and re-check, tiles scored)."""
     import torch
     from . import fh
-    sw.batch.launch()  # the maps of this evaluation
+    sw.batch.launch()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cands = sw.batch.select(sq[0], sq[1], 3, as_dicts=False)  # every map in one batched pass
     t_sel = time.perf_counter() - t0
-    props = None
-    t_prop = 0.0
-    n_tiles = 0
-    if net is not None:
-        t0 = time.perf_counter()
-        tops, tbs = [], []
-        for m in sw.maps:
-            ta, tb = (m["plan"].n_k + 63) // 64, (m["plan"].n_x0 + 63) // 64
-            tops.append(max(1, int(math.ceil(top_frac * ta * tb))))
-            tbs.append(tb)
-            n_tiles += ta * tb
-        _, best = fh.fh_batch_propose(net, sw.batch, tops)  # every map's tiles through the network at once
-        props = [(set(b), tb) for b, tb in zip(best, tbs)]
-        t_prop = time.perf_counter() - t0
-    # injections' true cells, per map
+    if net is None:
+        return cands, None, t_sel, 0.0, 0
+    t0 = time.perf_counter()
+    tops, n_tiles = [], 0
+    for m in sw.maps:
+        ta, tb = (m["plan"].n_k + 63) // 64, (m["plan"].n_x0 + 63) // 64
+        tops.append(max(1, int(math.ceil(top_frac * ta * tb))))
+        n_tiles += ta * tb
+    _, best = fh.fh_batch_propose(net, sw.batch, tops)  # every map's tiles through the network at once
+    req = [(mi, t) for mi, b in enumerate(best) for t in b]
+    rc, counts, _ = sw.batch.select_tiles(req, TILE_SQ[0], TILE_SQ[1], 3)
+    parts = [[] for _ in sw.maps]
+    at = 0
+    for (mi, _), c in zip(req, counts):
+        parts[mi].append(rc[at:at + c])
+        at += c
+    learned = [np.concatenate(x) if x else rc[:0] for x in parts]
+    return cands, learned, t_sel, time.perf_counter() - t0, n_tiles
+
+
+def _truth(sw: Sweep):
+    """Per map: the true cells (row, column) of its injections."""
     truth: Dict[int, List] = {}
     for (b, ti, ni, f0, k, amp, row) in sw.injections:
         mi = sw.map_index(b, ti, ni)
@@ -187,72 +202,56 @@ def evaluate(sw: Sweep, net=None, sq=(8, 8), top_frac: float = 0.1, thresholds=(
         info = m["plan"].info
         col = (f0 ** (1.0 - m["n"]) - info.x0_min) / info.dx0
         truth.setdefault(mi, []).append((row, col))
+    return truth
+
+
+def evaluate(sw: Sweep, net=None, sq=(8, 8), top_frac: float = 0.1, thresholds=(4.0, 5.0, 6.0)):
+    """The plain selection on every map and, with a network, the learned
+    pipeline (its proposals re-checked by the selection); efficiencies of both
+    and their noise candidates at each CR threshold."""
+    cands, learned, t_sel, t_prop, n_tiles = _run_pipelines(sw, net, sq, top_frac)
+    truth = _truth(sw)
     res = {"select_s": t_sel, "propose_s": t_prop, "tiles": n_tiles, "curves": []}
     noise_plain = {thr: 0 for thr in thresholds}
     noise_learn = {thr: 0 for thr in thresholds}
     det_plain = {thr: 0 for thr in thresholds}
     det_learn = {thr: 0 for thr in thresholds}
+
+    def far(c, tr):
+        return not tr or min(math.hypot(float(c["row"]) + 0.5 - r, float(c["col"]) + 0.5 - x) for (r, x) in tr) > 10.0
+
+    def hit(cl, thr, r, x):
+        return any(float(c["cr"]) >= thr and math.hypot(float(c["row"]) + 0.5 - r, float(c["col"]) + 0.5 - x) <= 3.0
+                   for c in cl)
+
     for mi, cl in enumerate(cands):
         tr = truth.get(mi, [])
-        keep = props[mi] if props is not None else None
-        for c in cl:
-            near = [math.hypot(c["row"] + 0.5 - r, c["col"] + 0.5 - x) for (r, x) in tr]
-            in_prop = keep is None or (c["row"] // 64) * keep[1] + (c["col"] // 64) in keep[0]
-            if not near or min(near) > 10.0:
-                for thr in thresholds:
-                    if c["cr"] >= thr:
-                        noise_plain[thr] += 1
-                        noise_learn[thr] += in_prop
-        for (r, x) in tr:
-            for thr in thresholds:
-                hits = [c for c in cl if c["cr"] >= thr and math.hypot(c["row"] + 0.5 - r, c["col"] + 0.5 - x) <= 3.0]
-                det_plain[thr] += bool(hits)
-                det_learn[thr] += any(keep is None or (c["row"] // 64) * keep[1] + (c["col"] // 64) in keep[0]
-                                      for c in hits)
+        lc = learned[mi] if learned is not None else []
+        for thr in thresholds:
+            noise_plain[thr] += sum(1 for c in cl if c["cr"] >= thr and far(c, tr))
+            noise_learn[thr] += sum(1 for c in lc if c["cr"] >= thr and far(c, tr))
+            for (r, x) in tr:
+                det_plain[thr] += hit(cl, thr, r, x)
+                det_learn[thr] += hit(lc, thr, r, x)
     n_inj = len(sw.injections)
     for thr in thresholds:
         res["curves"].append({"cr_thr": thr, "eff_plain": det_plain[thr] / n_inj,
-                              "eff_learned": det_learn[thr] / n_inj if props is not None else None,
+                              "eff_learned": det_learn[thr] / n_inj if learned is not None else None,
                               "noise_cands_plain": noise_plain[thr],
-                              "noise_cands_learned": noise_learn[thr] if props is not None else None})
+                              "noise_cands_learned": noise_learn[thr] if learned is not None else None})
     return res
 
 
-def _in_proposal(c, keep) -> bool:
-    return keep is None or (int(c["row"]) // 64) * keep[1] + (int(c["col"]) // 64) in keep[0]
-
-
-def _run_pipelines(sw: Sweep, net, sq, top_frac: float):
-    """Launch the batch, select on every map and, with a network, propose its
-    top tiles: (candidate records per map, (proposed tile set, tiles along x0)
-    per map or None)."""
-    import torch
-    from . import fh
-    sw.batch.launch()
-    torch.cuda.synchronize()
-    cands = sw.batch.select(sq[0], sq[1], 3, as_dicts=False)
-    if net is None:
-        return cands, None
-    tops, tbs = [], []
-    for m in sw.maps:
-        ta, tb = (m["plan"].n_k + 63) // 64, (m["plan"].n_x0 + 63) // 64
-        tops.append(max(1, int(math.ceil(top_frac * ta * tb))))
-        tbs.append(tb)
-    _, best = fh.fh_batch_propose(net, sw.batch, tops)
-    return cands, [(set(b), tb) for b, tb in zip(best, tbs)]
-
-
 def map_maxima(sw: Sweep, net, sq=(8, 8), top_frac: float = 0.1) -> np.ndarray:
-    """Per map: the largest CR of all its candidates (plain pipeline) and of its
-    candidates inside the proposed tiles (learned pipeline); -inf for none."""
-    cands, props = _run_pipelines(sw, net, sq, top_frac)
+    """Per map: the largest CR of the plain selection's candidates and of the
+    learned pipeline's (the re-check of the proposed tiles); -inf for none."""
+    cands, learned, _, _, _ = _run_pipelines(sw, net, sq, top_frac)
     out = np.full((len(cands), 2), -np.inf)
     for mi, cl in enumerate(cands):
-        keep = props[mi] if props is not None else None
-        for c in cl:
-            out[mi, 0] = max(out[mi, 0], float(c["cr"]))
-            if _in_proposal(c, keep):
-                out[mi, 1] = max(out[mi, 1], float(c["cr"]))
+        if len(cl):
+            out[mi, 0] = float(cl["cr"].max())
+        if learned is not None and len(learned[mi]):
+            out[mi, 1] = float(learned[mi]["cr"].max())
     return out
 
 
@@ -278,19 +277,18 @@ def evaluate_at_fap(dev, net, faps, n_noise_sweeps: int, seed: int, sw: Optional
     own = sw is None
     if own:
         sw = Sweep(dev, seed=seed, **kw)
-    cands, props = _run_pipelines(sw, net, sq, top_frac)
-    # per injection: the largest CR near its true cell, over all candidates and inside the proposals
+    cands, learned, _, _, _ = _run_pipelines(sw, net, sq, top_frac)
+    # per injection: the largest CR near its true cell, of each pipeline's candidates
     best = np.full((len(sw.injections), 2), -np.inf)
     for i, (b, ti, ni, f0, k, amp, row) in enumerate(sw.injections):
         mi = sw.map_index(b, ti, ni)
         m = sw.maps[mi]
         info = m["plan"].info
         col = (f0 ** (1.0 - m["n"]) - info.x0_min) / info.dx0
-        for c in cands[mi]:
-            if math.hypot(float(c["row"]) + 0.5 - row, float(c["col"]) + 0.5 - col) <= 3.0:
-                best[i, 0] = max(best[i, 0], float(c["cr"]))
-                if _in_proposal(c, props[mi]):
-                    best[i, 1] = max(best[i, 1], float(c["cr"]))
+        for q, cl in enumerate((cands[mi], learned[mi] if learned is not None else [])):
+            for c in cl:
+                if math.hypot(float(c["row"]) + 0.5 - row, float(c["col"]) + 0.5 - col) <= 3.0:
+                    best[i, q] = max(best[i, q], float(c["cr"]))
     amps = np.array([inj[5] for inj in sw.injections])
     if own:
         sw.destroy()

@@ -135,3 +135,80 @@ def test_select_rejects_bad_options(dev):
                dict(sq_k=1, sq_x0=1, col_lo=10, col_hi=5), dict(sq_k=1, sq_x0=300)):
         with pytest.raises(fh.FHError):
             fh.fh_select(plan, H, **kw)
+
+
+def _oracle_tile(OS, H, k, x0m, dx, n, t, sq, col_lo=0, col_hi=0):
+    """The oracle's selection applied to tile t's rectangle as a map of its own."""
+    n_k, n_x0 = H.shape
+    tb = (n_x0 + 63) // 64
+    a, b = divmod(t, tb)
+    r0, r1 = 64 * a, min(64 * a + 64, n_k)
+    c0 = max(64 * b, col_lo)
+    c1 = min(64 * b + 64, n_x0, col_hi if col_hi > 0 else n_x0)
+    if c0 >= c1:
+        return []
+    sub = np.ascontiguousarray(H[r0:r1])
+    out = OS.select(sub, np.asarray(k)[r0:r1], x0m, dx, n, sq[0], sq[1], sq[2], col_lo=c0, col_hi=c1)
+    for c in out:
+        c["row"] += r0
+    return out
+
+
+def test_select_tiles_against_oracle(dev, oracle):
+    import torch
+    from paper_1810_09784_amd import fh
+    from oracle import select as OS
+    spec = S.cfg_single_small()
+    pm = S.make_peakmap(spec)
+    plan = fh.Plan.from_spec(spec)
+    H = fh.fh_hough(plan, torch.from_numpy(pm.row_ptr).to(dev), torch.from_numpy(pm.bin).to(dev))
+    ref_map = oracle.hough(oracle.Desc.from_spec(spec), pm.row_ptr, pm.bin)
+    assert np.array_equal(H.cpu().numpy(), ref_map)
+    _, x0m, dx, _ = oracle.grid(oracle.Desc.from_spec(spec))
+    tiles = [0, 5, 7, 11, 3]  # tile 5 and 11: the last 3 columns of the 323
+    keys = ("row", "col", "count", "square", "second", "cr", "mu", "sigma", "x0", "k", "f0", "fdot0")
+    for sq, cols in (((2, 1, 3), (0, 0)), ((2, 2, 3), (0, 0)), ((1, 1, 0), (10, 300))):
+        got, counts, n = fh.fh_select_tiles(plan, H, tiles, *sq, col_lo=cols[0], col_hi=cols[1])
+        ref = []
+        for t in tiles:
+            r = _oracle_tile(OS, ref_map, spec.k, x0m, dx, spec.n, t, sq, *cols)
+            ref += r
+            assert counts[tiles.index(t)] == len(r)
+        assert n == len(ref) == len(got)
+        for g, r in zip(got, ref):
+            assert tuple(g[x] for x in keys) == tuple(r[x] for x in keys), (sq, g, r)
+    # tile 5 lies outside columns [10, 300): no candidate from it
+    _, counts, _ = fh.fh_select_tiles(plan, H, [5], 1, 1, 0, col_lo=10, col_hi=300)
+    assert counts[0] == 0
+    with pytest.raises(fh.FHError):
+        fh.fh_select_tiles(plan, H, [12], 2, 2)  # 2 x 6 tiles: index 12 is outside
+    with pytest.raises(fh.FHError):
+        fh.fh_select_tiles(plan, H, [0], 65, 1)  # more squares than the tile has rows
+
+
+def test_batch_select_tiles_equals_per_map(dev):
+    import torch
+    from paper_1810_09784_amd import fh
+    rng = np.random.default_rng(23)
+    specs = [S.cfg_tiny(rng, n_fft=400, n_f=80 + 40 * i, n_k=70 + 30 * i, n=3.0 + i, f_min=200.0 + 100 * i)
+             for i in range(3)]
+    plans, peaks, maps = [], [], []
+    for s in specs:
+        pm = S.make_peakmap(s)
+        plans.append(fh.Plan.from_spec(s))
+        peaks.append((torch.from_numpy(pm.row_ptr).to(dev), torch.from_numpy(pm.bin).to(dev)))
+        maps.append(torch.empty((plans[-1].n_k, plans[-1].n_x0), dtype=torch.int32, device=dev))
+    b = fh.Batch(plans, peaks, maps)
+    b.launch()
+    torch.cuda.synchronize()
+    tb = [(p.n_x0 + 63) // 64 for p in plans]
+    req = [(0, 1), (2, 2 * tb[2] - 1), (1, 0), (0, 1), (1, tb[1])]
+    got, counts, n = b.select_tiles(req, 2, 1, 3, cr_thr=1.5)
+    at = 0
+    for q, (mi, t) in enumerate(req):
+        ref, rc, rn = fh.fh_select_tiles(plans[mi], maps[mi], [t], 2, 1, 3, cr_thr=1.5, as_dicts=False)
+        assert counts[q] == rn == rc[0]
+        assert np.array_equal(got[at:at + rn], ref)
+        at += rn
+    assert at == n
+    b.destroy()
