@@ -32,6 +32,7 @@ HBM_PEAK_GBPS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 BF16_PEAK_TFLOPS = 2500.0  # dense matrix cores
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_k_queue_large_map.md")
+BATCH_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "traffic_k_queue_batch48.md")
 KERNEL_SOURCES = ("paper_1810_09784_amd/csrc/fh_hough.hip", "paper_1810_09784_amd/csrc/fh_plan.cpp",
                   "paper_1810_09784_amd/csrc/fh_internal.h")
 
@@ -67,13 +68,13 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the tile kernel from the committed counter summary
+def measured_traffic(path=TRAFFIC_PROFILE):
+    """HBM bytes per launch of a tile kernel from a committed counter summary
     (FETCH_SIZE and WRITE_SIZE, copy-calibrated), or None when the kernel sources
     changed since the counters were taken."""
     import re
     try:
-        with open(TRAFFIC_PROFILE) as f:
+        with open(path) as f:
             txt = f.read()
     except OSError:
         return None
@@ -335,11 +336,23 @@ def run_batched(fh, synth, tune, ceilings, dev, stream, K, W, check_oracle, plai
         batch_t.destroy()
         batch.launch(stream)  # the maps checked below are the batch's
     log(f"batched graph {ms_b:.4f} ms, plain per-map {ms_p:.4f} ms")
+    # HBM roofline of the batch: algorithmic bytes = every map stored once, every
+    # map's peaks, CSR and tables read once, over the graph launch's time (the
+    # clearing prologue and the persistent queue kernel; HIP events on its stream)
+    alg_b = sum(4 * pl.n_k * pl.n_x0 + 4 * p.n_peaks + 4 * (s.n_fft + 1) + 8 * (pl.n_f + 1) + 8 * pl.n_k + 8 * s.n_fft
+                for s, p, pl in zip(specs, pms, plans))
+    ach_b = alg_b / (ms_b * 1e-3) / 1e9
+    roof_b = {"bound": "hbm", "achieved": round(ach_b, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+              "frac": round(ach_b / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(BATCH_TRAFFIC_PROFILE),
+              "kernel": "fh::k_queue (the batch's persistent queue kernel, "
+                        + (f"{plans[0].tile['threads']}-thread work-groups)"
+                           if len({pl.tile["threads"] for pl in plans}) == 1 else "the library's shared work-group size)"),
+              "alg_bytes": alg_b, "timing": "the whole graph launch (prologue + queue kernel), HIP events"}
     out.update({"workload": "48 uneven maps (n x T_FFT x 2 seeds, 64 Hz bands, 2 h - 3 d, 64-1024 k)",
                 "tiles": "autotuned for the batch's graph launch" if tiles_b else "the library's own shapes",
                 "plain": "fh_hough map by map, each with its autotuned tile shape",
                 "updates_per_launch": Ub, "ms_batched": round(ms_b, 5),
-                "updates_per_s_batched": Ub / (ms_b * 1e-3)})
+                "updates_per_s_batched": Ub / (ms_b * 1e-3), "roofline": roof_b})
     if plain:
         out.update({"ms_plain": round(ms_p, 5), "updates_per_s_plain": Ub / (ms_p * 1e-3),
                     "speedup_vs_plain": round(ms_p / ms_b, 3)})
@@ -356,10 +369,16 @@ def run_batched(fh, synth, tune, ceilings, dev, stream, K, W, check_oracle, plai
         s_b = ms_b * 1e-3
         work_b = {"in_grid_pairs": pairs_b, "in_grid_fraction": round(pairs_b / Ub, 5),
                   "in_grid_pairs_per_s": pairs_b / s_b, "lds_atomic_lane_ops_per_s": 2 * pairs_b / s_b}
+        lds_peak = 32 * 256 * 2.4e9  # LDS atomic lane-ops/s: 32 lanes/clk/CU, 256 CUs, 2.4 GHz
+        work_b["lds_atomic_roof"] = {"achieved": round(2 * pairs_b / s_b / 1e12, 4), "peak": round(lds_peak / 1e12, 3),
+                                     "unit": "T atomic lane-ops/s", "frac": round(2 * pairs_b / s_b / lds_peak, 4),
+                                     "peak_basis": "32 lanes/clk/CU x 256 CUs x 2.4 GHz"}
         ceil_b = ceilings.load()
         if ceil_b:
             l_m = ceil_b["tests"]["lds_atomic_add_random"]["g_lane_ops_per_s"] * 1e9
             work_b["lds_atomic_frac_measured"] = round(2 * pairs_b / s_b / l_m, 4)
+            work_b["lds_atomic_roof"].update(measured_peak_random=round(l_m / 1e12, 3),
+                                             frac_measured=round(2 * pairs_b / s_b / l_m, 4))
         out["work"] = work_b
         out["parity_vs_oracle"] = {"checked": f"all {len(specs)} maps", "equal": equal_b}
         log(f"batched: oracle on all maps in {time.perf_counter() - t:.1f} s, parity {equal_b}, "
