@@ -482,19 +482,39 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
     // C of the tile's rows through the scalar cache (uniform row index)
     const __attribute__((address_space(4))) double* Cg = (const __attribute__((address_space(4))) double*)M.C + X.r0;
     int prev_last = INT_MIN;  // bin of the previous chunk's last peak (bad-peak count)
+    // C of the tile's first eight rows, held for every chunk (most chunks reach no further)
+    double c_first[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) c_first[q] = Cg[q];
+    // waves claim blocks of 64 FFTs in order until the range is done, so that
+    // no wave idles while another still has several blocks to go; a wave claims
+    // its next block, and loads that block's CSR offsets, while it works on the
+    // current one (lane l < nb: start of FFT f0 + l; lanes >= nb: the block's end)
     int* claim = X.flags + 3;
-    for (;;) {
-      // waves claim blocks of 64 FFTs in order until the range is done, so
-      // that no wave idles while another still has several blocks to go
+    int f0_next = 0, rp_next = 0, rpe_next = 0;
+    auto claim_block = [&]() {
       int bi = 0;
       if (lane == 0) bi = atomicAdd(claim, 1);
-      const int f0 = i_start + kWave * uniform(__builtin_amdgcn_readlane(bi, 0));
+      f0_next = i_start + kWave * uniform(__builtin_amdgcn_readlane(bi, 0));
+      if (f0_next < i_end) {
+        const int nbn = min(kWave, i_end - f0_next);
+        rp_next = G.row_ptr[f0_next + min(lane, nbn)];
+        rpe_next = G.row_ptr[f0_next + nbn];
+      }
+    };
+    claim_block();
+    for (;;) {
+      const int f0 = f0_next;
       if (f0 >= i_end) break;
       const int nb = min(kWave, i_end - f0);
       const int fi = f0 + min(lane, nb - 1);
-      // lane l < nb: start of FFT f0 + l; lanes >= nb: the block's end
-      const int rp_l = min(max(G.row_ptr[f0 + min(lane, nb)], 0), M.n_peaks);
-      const int rp_e = uniform(min(max(G.row_ptr[f0 + nb], 0), M.n_peaks));
+      const int rp_l = min(max(rp_next, 0), M.n_peaks);
+      const int rp_e = uniform(min(max(rpe_next, 0), M.n_peaks));
+      const int Pa = uniform(rp_l);
+      const int Pb = max(rp_e, Pa);
+      // the first chunk's bins, loaded before the block's set-up
+      int j_next = Pa < Pb ? G.bin[min(Pa + lane, Pb - 1)] : 0;
+      claim_block();
       const double Tf = fft_time(M, G, fi);
       int rb = nrows;
       if (mono) {
@@ -516,16 +536,13 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
       S.rb[lane] = lane < nb ? rb : 0;
       S.mark[lane] = -1;
       wave_sync_lds();
-      const int Pa = uniform(S.rp[0]);
-      const int Pb = max(rp_e, Pa);
       int u_carry = 0;  // FFT of the previous chunk's last peak
-      int j_next = Pa < Pb ? G.bin[min(Pa + lane, Pb - 1)] : 0;  // the next chunk's bins, loaded one chunk ahead
       for (int pc = Pa; pc < Pb; pc += kWave) {
         const int p = pc + lane;
         const bool pv = p < Pb;
         const int pcl = pv ? p : Pa;
         const int j = j_next;
-        if (pc + kWave < Pb) j_next = G.bin[min(pc + kWave + lane, Pb - 1)];
+        if (pc + kWave < Pb) j_next = G.bin[min(pc + kWave + lane, Pb - 1)];  // one chunk ahead
         // FFT of each peak: every FFT marks the chunk position of its first peak,
         // and a running maximum over the lanes carries the marks forward
         const int sft = rp_l - pc;
@@ -536,6 +553,7 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
         const int u = wave_incl_max(max(mk, u_carry));
         u_carry = __builtin_amdgcn_readlane(u, 63);
         const double T = S.T[u];
+        const int rb_u = S.rb[u];
         const bool jv = pv && (unsigned)j < (unsigned)M.n_f;
         if (count_bad) {
           // a bad peak: bin outside [0, n_f) or not above the previous bin of its
@@ -551,16 +569,21 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
         const int jc = jv ? j : M.n_f;
         const double a_hi = ALDS ? A_s[jc] : G.A[jc];
         const double a_lo = ALDS ? A_s[jc + 1] : G.A[jc + 1];
-        // rows that can reach the tile: largest for the chunk's first FFT when
-        // the rows' FFT ranges nest, else the largest over the lanes
-        const int rmax = mono ? uniform(S.rb[uniform(u)]) : wave_max(S.rb[u]);
-        // eight rows per step, their C read with one scalar load (the table has
-        // kCPad entries of padding after the last row)
+        // rows that can reach the tile: largest for the chunk's first FFT (lane
+        // 0's) when the rows' FFT ranges nest, else the largest over the lanes
+        const int rmax = mono ? uniform(rb_u) : wave_max(rb_u);
+        // eight rows per step; past the first eight, their C read with one scalar
+        // load (the table has kCPad entries of padding after the last row)
         int* Drow = D - c0;
         for (int r = 0; r < rmax; r += 8, Drow += 8 * pitch) {
           double c[8];
+          if (r == 0) {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) c[q] = Cg[r + q];
+            for (int q = 0; q < 8; ++q) c[q] = c_first[q];
+          } else {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) c[q] = Cg[r + q];
+          }
 #pragma unroll
           for (int q = 0; q < 8; ++q)
             if (r + q < rmax) edge_update<ZERO_COL>(Drow + q * pitch, c[q], T, a_lo, a_hi, eb);
