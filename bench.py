@@ -85,6 +85,21 @@ def measured_traffic(path=TRAFFIC_PROFILE):
     return int(m_b.group(1))
 
 
+def machine():
+    """The host and GPU the line was measured on."""
+    import torch
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    p = torch.cuda.get_device_properties(0)
+    return {"gpu": p.name, "gpu_arch": getattr(p, "gcnArchName", ""), "gpu_cus": p.multi_processor_count,
+            "gpu_mem_gib": round(p.total_memory / 2**30, 1), "host_cpu": cpu,
+            "host_threads": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()}
+
+
 def timed(fn, K, W, stream):
     import torch
     for _ in range(W):
@@ -601,6 +616,7 @@ def main():
         "step_unfused_serial_updates_per_s": U / (ms_serial * 1e-3),
         "hough_only_updates_per_s": U / (ms_hough * 1e-3),
         "roofline": roof,
+        "machine": machine(),
     }
 
     # ---------------------------------------------------- batched (48 maps) --

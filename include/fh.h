@@ -260,6 +260,15 @@ fh_status fh_cnn_get_params(fh_cnn_t net, float* params, float* grads, int64_t n
  * library (several processes' gradients summed before one step) and for tests
  * of the optimiser alone.  Synchronous.  Errors: FH_EINVAL, FH_EDEVICE. */
 fh_status fh_cnn_set_grads(fh_cnn_t net, const float* grads, int64_t n);
+/* Adam's state, for a training checkpoint: HOST copies of the first and second
+ * moments (float [n] in the flat order, n = 60289; either may be NULL) and the
+ * number of steps taken (may be NULL).  Synchronous.  Errors: FH_EINVAL, FH_EDEVICE. */
+fh_status fh_cnn_get_state(fh_cnn_t net, float* m1, float* m2, int64_t n, int64_t* steps);
+/* Restore that state (after fh_cnn_set_params, which resets it): the next
+ * fh_cnn_step continues as the network that saved it would have (bias
+ * corrections of step `steps` + 1).  0 <= steps < 2^31.  Synchronous.
+ * Errors: FH_EINVAL, FH_EDEVICE. */
+fh_status fh_cnn_set_state(fh_cnn_t net, const float* m1, const float* m2, int64_t n, int64_t steps);
 /* HOST copy of the BF16 activations of the last forward: layer 0 = the input
  * tiles [B][64][64], layer l = 1..4 = the ReLU output of conv l, NHWC
  * [B][64][64][C_l] with C = 16, 32, 64, 64 (B of that forward; n must equal

@@ -847,6 +847,28 @@ extern "C" fh_status fh_cnn_set_grads(fh_cnn_t h, const float* grads_host, int64
   return hipMemcpy(c->grads, grads_host, NPARAM * 4, hipMemcpyHostToDevice) == hipSuccess ? FH_OK : FH_EDEVICE;
 }
 
+extern "C" fh_status fh_cnn_get_state(fh_cnn_t h, float* m1_host, float* m2_host, int64_t n, int64_t* steps) {
+  if (!h || n != NPARAM) return FH_EINVAL;
+  fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);
+  if (hipDeviceSynchronize() != hipSuccess) return FH_EDEVICE;
+  if (m1_host && hipMemcpy(m1_host, c->m1, NPARAM * 4, hipMemcpyDeviceToHost) != hipSuccess) return FH_EDEVICE;
+  if (m2_host && hipMemcpy(m2_host, c->m2, NPARAM * 4, hipMemcpyDeviceToHost) != hipSuccess) return FH_EDEVICE;
+  if (steps) *steps = c->steps;
+  return FH_OK;
+}
+
+extern "C" fh_status fh_cnn_set_state(fh_cnn_t h, const float* m1_host, const float* m2_host, int64_t n,
+                                      int64_t steps) {
+  if (!h || !m1_host || !m2_host || n != NPARAM || steps < 0 || steps > INT32_MAX) return FH_EINVAL;
+  fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);
+  if (hipDeviceSynchronize() != hipSuccess) return FH_EDEVICE;
+  if (hipMemcpy(c->m1, m1_host, NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->m2, m2_host, NPARAM * 4, hipMemcpyHostToDevice) != hipSuccess)
+    return FH_EDEVICE;
+  c->steps = (int)steps;
+  return FH_OK;
+}
+
 extern "C" fh_status fh_cnn_activations(fh_cnn_t h, int32_t layer, uint16_t* out_host, int64_t n) {
   if (!h || !out_host || layer < 0 || layer > 4) return FH_EINVAL;
   fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);

@@ -110,6 +110,8 @@ SIGNATURES = {
     "fh_cnn_backward": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "fh_cnn_step": (C.c_int, [C.c_void_p, C.c_float, C.c_void_p]),
     "fh_cnn_set_grads": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
+    "fh_cnn_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
+    "fh_cnn_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64]),
     "fh_cnn_activations": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
     "fh_tiles": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
@@ -516,6 +518,22 @@ class CNN:
         a = np.ascontiguousarray(grads, dtype=np.float32)
         assert a.size == self.n_params
         _check(lib().fh_cnn_set_grads(self.handle, a.ctypes.data, a.size), "fh_cnn_set_grads")
+
+    def get_state(self):
+        """Adam's moments and step count: (m1, m2, steps)."""
+        m1 = np.empty(self.n_params, dtype=np.float32)
+        m2 = np.empty(self.n_params, dtype=np.float32)
+        st = C.c_int64()
+        _check(lib().fh_cnn_get_state(self.handle, m1.ctypes.data, m2.ctypes.data, m1.size, C.byref(st)),
+               "fh_cnn_get_state")
+        return m1, m2, int(st.value)
+
+    def set_state(self, m1, m2, steps: int):
+        a = np.ascontiguousarray(m1, dtype=np.float32)
+        b = np.ascontiguousarray(m2, dtype=np.float32)
+        assert a.size == b.size == self.n_params
+        _check(lib().fh_cnn_set_state(self.handle, a.ctypes.data, b.ctypes.data, a.size, int(steps)),
+               "fh_cnn_set_state")
 
     def activations(self, layer: int, batch: int):
         """BF16 activations of the last forward (layer 0: input, 1..4: conv outputs)

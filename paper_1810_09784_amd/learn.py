@@ -30,6 +30,7 @@ per batch)."""
 from __future__ import annotations
 
 import math
+import os
 from typing import Dict, List, Tuple
 
 import numpy as np
@@ -140,13 +141,33 @@ def build_training_set(dev, n_pos: int, n_neg_maps: int, seed: int, batch: int =
     return X, y
 
 
-def train(net, X, y, epochs: int, lr: float, batch: int, seed: int, log=None) -> List[float]:
+def train(net, X, y, epochs: int, lr: float, batch: int, seed: int, log=None, checkpoint: str = None,
+          after_epoch=None) -> List[float]:
+    """Adam over shuffled batches (the order drawn from `seed`); returns the mean
+    loss of every epoch.  checkpoint: path of an .npz written after every epoch
+    (parameters, Adam moments and step count, the epoch, the batch-order
+    generator's state and the losses so far, with the run's seed, batch, lr and
+    sample count); when it exists the run resumes after its epoch, and a file
+    from another run (different seed, batch, lr or samples) raises ValueError.
+    after_epoch(ep) is called once an epoch's checkpoint is written."""
     import torch
     g = torch.Generator(device="cpu")
     g.manual_seed(seed)
     n = X.shape[0]
-    hist = []
-    for ep in range(epochs):
+    hist, start = [], 0
+    run = np.array([seed, batch, n], dtype=np.int64)
+    if checkpoint and os.path.exists(checkpoint):
+        with np.load(checkpoint) as ck:
+            if not (np.array_equal(ck["run"], run) and float(ck["lr"]) == float(lr)):
+                raise ValueError(f"{checkpoint} belongs to another training run")
+            net.set_params(ck["params"])
+            net.set_state(ck["m1"], ck["m2"], int(ck["steps"]))
+            g.set_state(torch.from_numpy(ck["rng"].copy()))
+            hist = [float(v) for v in ck["hist"]]
+            start = int(ck["epoch"]) + 1
+        if log:
+            log(f"resumed from {checkpoint} after epoch {start - 1}")
+    for ep in range(start, epochs):
         perm = torch.randperm(n, generator=g).to(X.device)
         tot, cnt = 0.0, 0
         for b0 in range(0, n - batch + 1, batch):
@@ -159,6 +180,16 @@ def train(net, X, y, epochs: int, lr: float, batch: int, seed: int, log=None) ->
         hist.append(tot / max(cnt, 1))
         if log:
             log(f"epoch {ep}: loss {hist[-1]:.4f}")
+        if checkpoint:
+            params, _ = net.get_params()
+            m1, m2, steps = net.get_state()
+            tmp = checkpoint + ".tmp.npz"
+            np.savez(tmp, params=params, m1=m1, m2=m2, steps=np.int64(steps), epoch=np.int64(ep),
+                     rng=g.get_state().numpy(), hist=np.asarray(hist, dtype=np.float64), run=run,
+                     lr=np.float64(lr))
+            os.replace(tmp, checkpoint)  # a run killed while writing keeps the previous epoch's file
+        if after_epoch:
+            after_epoch(ep)
     return hist
 
 

@@ -30,6 +30,8 @@ def main():
     ap.add_argument("--fap", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--weights", default=None, help="skip training, evaluate these parameters")
+    ap.add_argument("--checkpoint", default=None,
+                    help="training checkpoint (.npz) written after every epoch; an existing one is resumed")
     ap.add_argument("--geometry", default="small", choices=("small", "sweep"),
                     help="small: the n = 5, 500-600 Hz maps; sweep: the full sweep's maps")
     ap.add_argument("--sweep-maps", type=int, default=1250, help="training peakmaps of the sweep geometry")
@@ -67,7 +69,7 @@ def main():
         torch.cuda.synchronize()
         log(f"training set: {X.shape[0]} tiles ({int(y.sum().item())} positive) in {time.time() - t:.1f} s")
         t = time.time()
-        hist = learn.train(net, X, y, a.epochs, a.lr, a.batch, a.seed, log=log)
+        hist = learn.train(net, X, y, a.epochs, a.lr, a.batch, a.seed, log=log, checkpoint=a.checkpoint)
         torch.cuda.synchronize()
         dt = time.time() - t
         steps = a.epochs * (X.shape[0] // a.batch)
