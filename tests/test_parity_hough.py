@@ -310,3 +310,54 @@ def test_batched_small_maps_full_compare(dev, oracle):
     for q, s in enumerate(specs):
         ref = oracle.hough(oracle.Desc.from_spec(s), pms[q].row_ptr, pms[q].bin)
         assert_maps_equal(maps[q].cpu().numpy(), ref, f"{s.name} tile={plans[q].tile}")
+
+
+def test_maximum_size_map(dev, oracle):
+    # the largest map a plan accepts: n_k n_x0 just below 2^31 cells (8.6 GB of
+    # int32), 1023 rows x 2099202 columns of an x0 grid 30000 times finer than
+    # the natural one; sampled rows cell by cell, every row's total, and the
+    # selection's best cells against the map (properties that hold at any size)
+    import torch
+    from paper_1810_09784_amd import fh
+    rng = np.random.default_rng(81)
+    spec = S.cfg_tiny(rng, n_fft=400, n_f=60, n_k=1023, n=3.0, tfft=2.0, f_min=300.0, kscale=0.5)
+    pm = S.make_peakmap(spec)
+    d0 = oracle.Desc.from_spec(spec)
+    nf, x0m, dx, nx = oracle.grid(d0)
+    n_x0 = (2**31 - 1) // spec.n_k
+    kw = dict(x0_min=x0m, dx0=dx * nx / n_x0, n_x0=n_x0)
+    assert spec.n_k * n_x0 < 2**31 <= spec.n_k * (n_x0 + 1)
+    plan = fh.Plan(spec.n, spec.tfft, spec.f_min, spec.f_max, spec.n_fft, spec.k, **kw)
+    assert (plan.n_k, plan.n_x0) == (spec.n_k, n_x0)
+    rp, bn = _to_dev(pm, dev)
+    out = torch.full((plan.n_k, plan.n_x0), -7, dtype=torch.int32, device=dev)
+    print(f"maximum-size map {plan.n_k} x {plan.n_x0}, tile {plan.tile}", flush=True)
+    fh.fh_hough(plan, rp, bn, out)
+    torch.cuda.synchronize()
+    assert fh.fh_device_errors(plan) == 0
+    assert (out.min() >= 0).item()
+    d = oracle.Desc.from_spec(spec, **kw)
+    rows = sorted(set([0, 1, 7, 8, 63, 64, 511, 1022] + list(rng.integers(0, spec.n_k, 4))))
+    ref_rows, _, _ = oracle.rows_checked(d, pm.row_ptr, pm.bin, np.asarray(rows, dtype=np.int32))
+    assert_maps_equal(out[rows].cpu().numpy(), ref_rows, "maximum-size map rows")
+    _, ref_tot, pairs = oracle.rows_checked(d, pm.row_ptr, pm.bin, np.arange(spec.n_k, dtype=np.int32),
+                                            with_map=False)
+    assert np.array_equal(out.sum(dim=1, dtype=torch.int64).cpu().numpy(), ref_tot)
+    assert int(pairs.sum()) > 0
+    # selection: each square's best cell is the square's maximum, first in row-major order
+    sq_k, sq_x0 = 5, 5
+    cands, n = fh.fh_select(plan, out, sq_k, sq_x0, 3)
+    assert n == len(cands) > 0
+    for c in cands:
+        a, b = divmod(c["square"], sq_x0)
+        r0, r1 = a * plan.n_k // sq_k, (a + 1) * plan.n_k // sq_k
+        c0, c1 = b * plan.n_x0 // sq_x0, (b + 1) * plan.n_x0 // sq_x0
+        assert r0 <= c["row"] < r1 and c0 <= c["col"] < c1
+        assert int(out[c["row"], c["col"]]) == c["count"]
+        if not c["second"]:
+            region = out[r0:r1, c0:c1]
+            assert int(region.max()) == c["count"]
+            first = torch.nonzero(region == c["count"])[0]
+            assert (c["row"], c["col"]) == (int(first[0]) + r0, int(first[1]) + c0)
+    del out
+    torch.cuda.empty_cache()
