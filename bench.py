@@ -217,6 +217,7 @@ def run_cnn(fh, dev, stream, B=256, reps=20):
     x = torch.from_numpy(rng.normal(0.0, 1.0, (B, 64, 64)).astype(np.float32)).to(dev).to(torch.bfloat16)
     lab = torch.from_numpy((rng.random(B) < 0.5).astype(np.float32)).to(dev)
     fwd = timed(lambda: net.forward(x, stream=stream), reps, 3, stream)
+    sco = timed(lambda: net.scores(x, stream=stream), reps, 3, stream)  # the proposals' forward
 
     def train():
         net.forward(x, stream=stream)
@@ -227,9 +228,12 @@ def run_cnn(fh, dev, stream, B=256, reps=20):
     net.destroy()
     f_fwd = 492.0e6 * B
     tf_fwd, tf_trn = f_fwd / (fwd * 1e-3) / 1e12, 3 * f_fwd / (trn * 1e-3) / 1e12
-    log(f"cnn: forward {fwd:.3f} ms / {B} tiles ({tf_fwd:.0f} TFLOP/s), training step {trn:.3f} ms "
-        f"({tf_trn:.0f} TFLOP/s)")
+    tf_sco = f_fwd / (sco * 1e-3) / 1e12
+    log(f"cnn: forward {fwd:.3f} ms / {B} tiles ({tf_fwd:.0f} TFLOP/s), proposals' forward {sco:.3f} ms "
+        f"({tf_sco:.0f} TFLOP/s), training step {trn:.3f} ms ({tf_trn:.0f} TFLOP/s)")
     return {"tiles_per_batch": B, "forward_ms": round(fwd, 4), "forward_tiles_per_s": B / (fwd * 1e-3),
+            "scores_ms": round(sco, 4), "scores_tiles_per_s": B / (sco * 1e-3), "scores_tflops": round(tf_sco, 1),
+            "scores_mfma_frac": round(tf_sco / BF16_PEAK_TFLOPS, 4),
             "forward_tflops": round(tf_fwd, 1), "train_step_ms": round(trn, 4), "train_tflops": round(tf_trn, 1),
             "peak_tflops": BF16_PEAK_TFLOPS, "forward_mfma_frac": round(tf_fwd / BF16_PEAK_TFLOPS, 4),
             "train_mfma_frac": round(tf_trn / BF16_PEAK_TFLOPS, 4), **_mfma_measured(tf_fwd, tf_trn)}

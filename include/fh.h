@@ -277,6 +277,11 @@ fh_status fh_cnn_set_state(fh_cnn_t net, const float* m1, const float* m2, int64
 fh_status fh_cnn_activations(fh_cnn_t net, int32_t layer, uint16_t* out, int64_t n);
 /* logits (DEVICE float [B], may be NULL) of B <= max_batch tiles; keeps the activations. */
 fh_status fh_cnn_forward(fh_cnn_t net, const uint16_t* tiles, int32_t B, float* logits, void* stream);
+/* Logits (DEVICE float [B]) of B <= max_batch tiles for proposals: the same
+ * arithmetic as fh_cnn_forward, bit for bit, but the last layer keeps only its
+ * per-row channel sums for the pool and its activations are not stored: a
+ * backward or fh_cnn_activations may not follow (they return FH_EINVAL).  Errors: FH_EINVAL, FH_ERANGE (B), FH_EDEVICE. */
+fh_status fh_cnn_scores(fh_cnn_t net, const uint16_t* tiles, int32_t B, float* logits, void* stream);
 /* Mean binary cross-entropy of the last forward against labels (DEVICE float [B], 0/1)
  * and its gradients (replacing the previous ones); loss: DEVICE float, may be NULL. */
 fh_status fh_cnn_backward(fh_cnn_t net, const float* labels, int32_t B, float* loss, void* stream);

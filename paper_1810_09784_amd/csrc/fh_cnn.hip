@@ -88,6 +88,10 @@ __device__ __forceinline__ f4 mfma(typename Frag<KW>::T a, typename Frag<KW>::T 
 //   FWD:  out = bf16(relu(bias + conv(in, w)))
 //   BWD:  out = bf16(conv(in, w) * (mask > 0))   (in = dY, w = flipped w^T,
 //         mask = the forward input of the layer: the ReLU derivative)
+// EPI (forward only): 0 stores out; 1 stores out and the row sums of every
+// output channel, rowsum[b][y][co] = sum over x of out (the global pool's
+// partial sums, added in a fixed order); 2 writes the row sums alone (the
+// last layer when nothing needs its activations).
 constexpr int kConvWaves = 8;       // output rows per group
 constexpr int kConvRowsPerWG = 32;  // output rows per work-group
 
@@ -116,10 +120,12 @@ __device__ __forceinline__ int row_swz(int co) {
   return GW == 1 ? 0 : (co / (8 / GW)) & (GW - 1);
 }
 
-template <int CIN, int COUT, bool BWD>
+template <int CIN, int COUT, bool BWD, int EPI = 0>
 __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restrict__ in, const bf16_t* __restrict__ w,
                                                           const float* __restrict__ bias,
-                                                          const bf16_t* __restrict__ mask, bf16_t* __restrict__ out) {
+                                                          const bf16_t* __restrict__ mask, bf16_t* __restrict__ out,
+                                                          float* __restrict__ rowsum) {
+  static_assert(!BWD || EPI == 0, "row sums of the forward output only");
   static_assert(CIN % 8 == 0 && (COUT * 9 * CIN) % 8 == 0 && HW % kConvRowsPerWG == 0 &&
                     kConvRowsPerWG % kConvWaves == 0, "conv layout");
   constexpr int K = 9 * CIN;
@@ -215,13 +221,14 @@ __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restri
     }
     const int y = y0 + wave;
 #pragma unroll
-    for (int pt = 0; pt < 4; ++pt)
+    for (int ct = 0; ct < NCT; ++ct) {
+      const int co = ct * 16 + m;
+      float rs = 0.f;  // this lane's 16 pixels of channel co (EPI > 0)
 #pragma unroll
-      for (int ct = 0; ct < NCT; ++ct)
+      for (int pt = 0; pt < 4; ++pt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int x = pt * 16 + g * 4 + i;
-          const int co = ct * 16 + m;
           const size_t o = ((size_t)y * HW + x) * COUT + co;
           float v = acc[pt][ct][i];
           if (BWD) {
@@ -229,8 +236,17 @@ __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restri
           } else {
             v = fmaxf(v + bias[co], 0.f);
           }
-          ob[o] = f2bf(v);
+          const bf16_t h = f2bf(v);
+          if constexpr (EPI != 2) ob[o] = h;
+          if constexpr (EPI != 0) rs += bf2f(h);
         }
+      if constexpr (EPI != 0) {
+        // the four lanes of channel co (g = 0..3) add their parts: (g0 + g1) + (g2 + g3)
+        rs += __shfl_xor(rs, 16);
+        rs += __shfl_xor(rs, 32);
+        if (g == 0) rowsum[((size_t)b * HW + y) * COUT + co] = rs;
+      }
+    }
   }
 }
 
@@ -464,48 +480,20 @@ __global__ void __launch_bounds__(256) k_conv1_wgrad(const bf16_t* __restrict__ 
 }
 
 // ------------------------------------------------------------------ head --
-// feat[b][c] = mean over pixels of act4; logit = feat . w5 + b5.  One
-// work-group per tile: thread t reads channels 8 (t % 8) .. +7 of pixels
-// t / 8 + 128 m (16-byte loads, eight in flight), the 128 partial sums of a
-// channel are added in LDS in a fixed order.
-constexpr int kHeadThreads = 1024;
-constexpr int kHeadLanes = kHeadThreads / 8;  // pixel lanes
-constexpr int kHeadUnroll = 8;
-
-__global__ void __launch_bounds__(kHeadThreads) k_head_fwd(const bf16_t* __restrict__ act4,
-                                                           const float* __restrict__ w5, const float* __restrict__ b5,
-                                                           float* __restrict__ feat, float* __restrict__ logit) {
-  static_assert(C4 == 64 && NPIX % (kHeadLanes * kHeadUnroll) == 0, "head layout");
-  __shared__ float part[kHeadLanes][C4];
-  const int b = blockIdx.x, t = threadIdx.x;
-  const int g = t & 7, pl = t >> 3;
-  const uint4* px = reinterpret_cast<const uint4*>(act4 + (size_t)b * NPIX * C4);  // 8 channels per uint4
-  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  for (int p0 = pl; p0 < NPIX; p0 += kHeadLanes * kHeadUnroll) {
-    uint4 v[kHeadUnroll];
-#pragma unroll
-    for (int u = 0; u < kHeadUnroll; ++u) v[u] = px[(size_t)(p0 + u * kHeadLanes) * 8 + g];
-#pragma unroll
-    for (int u = 0; u < kHeadUnroll; ++u) {
-      const unsigned w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        s[2 * k] += __uint_as_float(w[k] << 16);
-        s[2 * k + 1] += __uint_as_float(w[k] & 0xffff0000u);
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < 8; ++k) part[pl][8 * g + k] = s[k];
-  __syncthreads();
+// The head from the last layer's row sums: feat[b][c] = (sum over rows y in
+// order of rowsum[b][y][c]) / NPIX; logit = b5 + sum over c in order of
+// feat[c] w5[c].  One 64-thread work-group per tile.
+__global__ void __launch_bounds__(C4) k_head_pool(const float* __restrict__ rowsum, const float* __restrict__ w5,
+                                                  const float* __restrict__ b5, float* __restrict__ feat,
+                                                  float* __restrict__ logit) {
   __shared__ float red[C4];
-  if (t < C4) {
-    float f = 0.f;
-    for (int q = 0; q < kHeadLanes; ++q) f += part[q][t];
-    f *= 1.0f / NPIX;
-    feat[b * C4 + t] = f;
-    red[t] = f * w5[t];
-  }
+  const int b = blockIdx.x, t = threadIdx.x;
+  const float* rb = rowsum + (size_t)b * HW * C4 + t;
+  float f = 0.f;
+  for (int y = 0; y < HW; ++y) f += rb[(size_t)y * C4];
+  f *= 1.0f / NPIX;
+  feat[b * C4 + t] = f;
+  red[t] = f * w5[t];
   __syncthreads();
   if (t == 0) {
     float z = b5[0];
@@ -724,6 +712,7 @@ struct fh_cnn_s {
   bf16_t *x = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *a4 = nullptr;  // activations
   bf16_t *d1 = nullptr, *d2 = nullptr, *d3 = nullptr, *d4 = nullptr;               // activation gradients
   float *feat = nullptr, *logit = nullptr, *loss = nullptr;
+  float* rowsum = nullptr;  // [max_batch][64][64]: the last layer's row sums per channel
   float *row_mean = nullptr, *row_istd = nullptr;
   int row_cap = 0;
   int2* origins = nullptr;
@@ -747,20 +736,21 @@ void cnn_free(fh_cnn_s* c) {
   if (!c) return;
   void* ptrs[] = {c->params, c->grads, c->m1,  c->m2,   c->w1r, c->w2,    c->w3,    c->w4, c->w2t, c->w3t, c->w4t, c->x,
                   c->a1,     c->a2,    c->a3,  c->a4,   c->d1,    c->d2,    c->d3, c->d4,  c->feat, c->logit,
-                  c->loss,   c->row_mean, c->row_istd, c->origins, c->ptab};
+                  c->loss,   c->row_mean, c->row_istd, c->origins, c->ptab, c->rowsum};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
 }
 
-template <int CIN, int COUT, bool BWD>
+template <int CIN, int COUT, bool BWD, int EPI = 0>
 fh_status launch_conv(const bf16_t* in, const bf16_t* w, const float* bias, const bf16_t* mask, bf16_t* out, int B,
-                      hipStream_t s) {
+                      hipStream_t s, float* rowsum = nullptr) {
   constexpr int lds = conv_lds<CIN, COUT>();
-  (void)hipFuncSetAttribute((const void*)k_conv<CIN, COUT, BWD>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  (void)hipFuncSetAttribute((const void*)k_conv<CIN, COUT, BWD, EPI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds);
   static_assert(lds <= 160 * 1024, "conv LDS");
-  hipLaunchKernelGGL((k_conv<CIN, COUT, BWD>), dim3(B * (HW / kConvRowsPerWG)), dim3(kConvWaves * 64), lds, s, in, w,
-                     bias, mask, out);
+  hipLaunchKernelGGL((k_conv<CIN, COUT, BWD, EPI>), dim3(B * (HW / kConvRowsPerWG)), dim3(kConvWaves * 64), lds, s,
+                     in, w, bias, mask, out, rowsum);
   return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
 }
 
@@ -800,6 +790,7 @@ extern "C" fh_status fh_cnn_create(int32_t max_batch, fh_cnn_t* out) {
             dalloc(&c->a1, P * C1) && dalloc(&c->a2, P * C2) && dalloc(&c->a3, P * C3) && dalloc(&c->a4, P * C4) &&
             dalloc(&c->d1, P * C1) && dalloc(&c->d2, P * C2) && dalloc(&c->d3, P * C3) && dalloc(&c->d4, P * C4) &&
             dalloc(&c->feat, (size_t)max_batch * C4) && dalloc(&c->logit, max_batch) && dalloc(&c->loss, 1) &&
+            dalloc(&c->rowsum, (size_t)max_batch * HW * C4) &&
             dalloc(&c->origins, max_batch);
   if (!ok) {
     cnn_free(c);
@@ -893,14 +884,47 @@ extern "C" fh_status fh_cnn_forward(fh_cnn_t h, const uint16_t* tiles, int32_t B
   hipLaunchKernelGGL(k_conv1_fwd, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, c->x, c->w1r, c->a1, B);
   fh_status st = launch_conv<C1, C2, false>(c->a1, c->w2, c->params + OFF_B2, nullptr, c->a2, B, s);
   if (st == FH_OK) st = launch_conv<C2, C3, false>(c->a2, c->w3, c->params + OFF_B3, nullptr, c->a3, B, s);
-  if (st == FH_OK) st = launch_conv<C3, C4, false>(c->a3, c->w4, c->params + OFF_B4, nullptr, c->a4, B, s);
+  if (st == FH_OK)
+    st = launch_conv<C3, C4, false, 1>(c->a3, c->w4, c->params + OFF_B4, nullptr, c->a4, B, s, c->rowsum);
   if (st != FH_OK) return st;
-  hipLaunchKernelGGL(k_head_fwd, dim3(B), dim3(kHeadThreads), 0, s, c->a4, c->params + OFF_W5, c->params + OFF_B5,
-                     c->feat, c->logit);
+  hipLaunchKernelGGL(k_head_pool, dim3(B), dim3(C4), 0, s, c->rowsum, c->params + OFF_W5, c->params + OFF_B5, c->feat,
+                     c->logit);
   if (logits && hipMemcpyAsync(logits, c->logit, (size_t)B * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
     return FH_EDEVICE;
   c->last_batch = B;
   return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
+}
+
+
+namespace {
+// The forward for proposals: the same layers and the same logits as
+// fh_cnn_forward, but the last layer writes only its row sums (nothing will
+// take a gradient), so its 512 KB of activations per tile are neither stored
+// nor read back.  No backward may follow: the network's last batch is reset.
+fh_status forward_scores(fh_cnn_s* c, int B, float* logits, hipStream_t s) {
+  const long long npx = (long long)B * NPIX;
+  hipLaunchKernelGGL(k_conv1_fwd, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, s, c->x, c->w1r, c->a1, B);
+  fh_status st = launch_conv<C1, C2, false>(c->a1, c->w2, c->params + OFF_B2, nullptr, c->a2, B, s);
+  if (st == FH_OK) st = launch_conv<C2, C3, false>(c->a2, c->w3, c->params + OFF_B3, nullptr, c->a3, B, s);
+  if (st == FH_OK)
+    st = launch_conv<C3, C4, false, 2>(c->a3, c->w4, c->params + OFF_B4, nullptr, nullptr, B, s, c->rowsum);
+  if (st != FH_OK) return st;
+  hipLaunchKernelGGL(k_head_pool, dim3(B), dim3(C4), 0, s, c->rowsum, c->params + OFF_W5, c->params + OFF_B5, c->feat,
+                     logits);
+  c->last_batch = 0;
+  return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
+}
+}  // namespace
+
+extern "C" fh_status fh_cnn_scores(fh_cnn_t h, const uint16_t* tiles, int32_t B, float* logits, void* stream) {
+  if (!h || !tiles || !logits || B < 1) return FH_EINVAL;
+  fh_cnn_s* c = reinterpret_cast<fh_cnn_s*>(h);
+  if (B > c->max_batch) return FH_ERANGE;
+  hipStream_t s = (hipStream_t)stream;
+  if (tiles != c->x &&
+      hipMemcpyAsync(c->x, tiles, (size_t)B * NPIX * 2, hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return FH_EDEVICE;
+  return forward_scores(c, B, logits, s);
 }
 
 extern "C" fh_status fh_cnn_backward(fh_cnn_t h, const float* labels, int32_t B, float* loss, void* stream) {
@@ -976,7 +1000,7 @@ extern "C" fh_status fh_propose(fh_cnn_t h, fh_plan_t ph, const int32_t* map, fl
     hipLaunchKernelGGL(k_gather, dim3(B), dim3(256), 0, s, map, n_k, n_x0, c->row_mean, c->row_istd, c->origins,
                        c->x);
     // the network reads its input buffer in place
-    fh_status st = fh_cnn_forward(h, c->x, B, scores + t0, stream);
+    fh_status st = forward_scores(c, B, scores + t0, s);
     if (st != FH_OK) return st;
     // the origins buffer is reused by the next batch: finish this one first
     if (hipStreamSynchronize(s) != hipSuccess) return FH_EDEVICE;
@@ -1034,7 +1058,7 @@ extern "C" fh_status fh_batch_propose(fh_cnn_t h, fh_batch_t b, float* scores, c
   for (long long t0 = 0; t0 < tiles; t0 += c->max_batch) {
     const int B = (int)std::min<long long>(c->max_batch, tiles - t0);
     hipLaunchKernelGGL(k_gather_batch, dim3(B), dim3(256), 0, s, c->ptab, m, (int)t0, c->row_mean, c->row_istd, c->x);
-    const fh_status st = fh_cnn_forward(h, c->x, B, scores + t0, stream);
+    const fh_status st = forward_scores(c, B, scores + t0, s);
     if (st != FH_OK) return st;
   }
   std::vector<float> sc((size_t)tiles);

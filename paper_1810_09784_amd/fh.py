@@ -112,6 +112,7 @@ SIGNATURES = {
     "fh_cnn_set_grads": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64]),
     "fh_cnn_get_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.POINTER(C.c_int64)]),
     "fh_cnn_set_state": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64]),
+    "fh_cnn_scores": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
     "fh_cnn_activations": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int64]),
     "fh_tiles": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
                            C.c_void_p, C.c_void_p]),
@@ -552,6 +553,17 @@ class CNN:
             out = torch.empty(B, dtype=torch.float32, device=tiles.device)
         _check(lib().fh_cnn_forward(self.handle, C.c_void_p(_ptr(tiles)), B, C.c_void_p(_ptr(out)),
                                     _stream(stream)), "fh_cnn_forward")
+        return out
+
+    def scores(self, tiles, out=None, stream=None):
+        """fh_cnn_scores: the logits of fh_cnn_forward without keeping activations (no backward may follow)."""
+        import torch
+        assert tiles.dtype == torch.bfloat16 and tiles.is_contiguous() and tuple(tiles.shape[1:]) == (64, 64)
+        B = int(tiles.shape[0])
+        if out is None:
+            out = torch.empty(B, dtype=torch.float32, device=tiles.device)
+        _check(lib().fh_cnn_scores(self.handle, C.c_void_p(_ptr(tiles)), B, C.c_void_p(_ptr(out)), _stream(stream)),
+               "fh_cnn_scores")
         return out
 
     def backward(self, labels, stream=None):

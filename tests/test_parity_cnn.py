@@ -234,3 +234,26 @@ def test_propose_ranks_tiles_by_score(dev):
     # max_batch 8 < 12 tiles: fh_propose scores in pieces, so does this check
     lg = np.concatenate([net.forward(tiles[i:i + 8].contiguous()).cpu().numpy() for i in (0, 8)])
     assert np.allclose(lg, sc, rtol=0, atol=1e-6)
+    # and the proposals' forward (fh_cnn_scores) gives fh_cnn_forward's logits bit for bit
+    np.testing.assert_array_equal(lg, sc)
+
+
+@pytest.mark.parametrize("seed,B", [(3, 1), (4, 8)])
+def test_scores_equal_forward_logits(dev, seed, B):
+    # fh_cnn_scores keeps only the last layer's row sums for the pool: the same
+    # logits as fh_cnn_forward, bit for bit, and no backward may follow it
+    from paper_1810_09784_amd import fh
+    from oracle import cnn as N
+    rng = np.random.default_rng(seed)
+    net = fh.CNN(max_batch=8)
+    net.set_params(N.init_params(rng))
+    xt = _to_bf16(dev, _tiles(rng, B))
+    lf = net.forward(xt).cpu().numpy()
+    ls = net.scores(xt).cpu().numpy()
+    np.testing.assert_array_equal(ls, lf)
+    import torch
+    with pytest.raises(fh.FHError):
+        net.backward(torch.zeros(B, dtype=torch.float32, device=dev))
+    with pytest.raises(fh.FHError):
+        net.activations(4, B)
+    net.destroy()
