@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--cnn-only", action="store_true",
+                    help="only the tile CNN section (forward, proposals' forward, training step), for profiling")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the 48-map batch's graph launches (no per-map launches, no oracle): for profiling")
     ap.add_argument("--no-sweep", action="store_true", help="skip the 990-map sweep and the search-layout extras")
@@ -449,6 +451,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
+    if a.cnn_only:
+        print(json.dumps({"cnn": run_cnn(fh, dev, stream)}), flush=True)
+        return
     if a.batched_only:
         b = run_batched(fh, synth, tune, ceilings, dev, stream, a.steps, a.warmup, False, plain=False)
         if a.copy_calibration:
