@@ -158,7 +158,8 @@ def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_
                  "note": "tile CNN trained on maps of this geometry drawn with other seeds (tile_cnn_sweep.npy)"}
     if parity:
         sweep_out.update(in_grid_pairs=parity["in_grid_pairs"],
-                         in_grid_pairs_per_s_batched=parity["in_grid_pairs"] / (ms_b * 1e-3))
+                         in_grid_pairs_per_s_batched=parity["in_grid_pairs"] / (ms_b * 1e-3),
+                         in_grid_pairs_per_s_plain=parity["in_grid_pairs"] / (ms_p * 1e-3))
     sw_paper = run_sweep_paper_k(fh, dev, stream, K, check_oracle)
     # coincidences: the sweep's candidates against a second draw of the same maps'
     # candidates is not available, so the list is joined with itself moved by one bin
@@ -185,6 +186,16 @@ def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_
     rpg, bng = torch.from_numpy(pm_g.row_ptr).to(dev), torch.from_numpy(pm_g.bin).to(dev)
     hg = torch.empty((plan_g.n_k, plan_g.n_x0), dtype=torch.int32, device=dev)
     ms_g = timed(lambda: fh.fh_hough(plan_g, rpg, bng, hg, stream), K, 2, stream)
+    grid_work = {}
+    if check_oracle:
+        from oracle import hough as oracle
+        d_g = oracle.Desc.from_spec(spec_g)
+        rows_g = np.arange(len(ks), dtype=np.int32)
+        _, tot_g, pairs_g = oracle.rows_checked(d_g, pm_g.row_ptr, pm_g.bin, rows_g, with_map=False)
+        ok_g = bool(np.array_equal(hg.sum(dim=1, dtype=torch.int64).cpu().numpy(), tot_g))
+        grid_work = {"in_grid_pairs": int(pairs_g.sum()), "in_grid_pairs_per_s": int(pairs_g.sum()) / (ms_g * 1e-3),
+                     "row_totals_equal_oracle": ok_g}
+        assert ok_g, "paper-grid map row totals differ from the oracle"
     # follow-up of the large map's candidates: projections and over-resolved maps
     lst = cands_large["list"]
     f0t = torch.tensor([float(c["f0"]) for c in lst], dtype=torch.float64, device=dev)
@@ -196,7 +207,8 @@ def run_sweep(fh, synth, dev, stream, cands_large, spec, plan, rp, bn, K, check_
     s_roi = time.perf_counter() - t_roi
     layout = {"paper_k_grid_map": {"workload": "n=5, 500-600 Hz, T_FFT=2 s, 7200 FFTs, geometric k grid "
                                                "(fdot 1e-3..1 x 1/T_FFT^2)", "k_rows": int(len(ks)),
-                                   "ms": round(ms_g, 4), "updates_per_s": pm_g.n_peaks * len(ks) / (ms_g * 1e-3)},
+                                   "ms": round(ms_g, 4), "updates_per_s": pm_g.n_peaks * len(ks) / (ms_g * 1e-3),
+                                   **grid_work},
               "coincide": {"points": len(pts), "segments": len(off) - 1, "ms": round(ms_c, 4)},
               "project": {"candidates": len(lst), "peaks": int(bn.numel()), "ms": round(ms_proj, 4),
                           "peak_moves_per_s": len(lst) * int(bn.numel()) / (ms_proj * 1e-3)},
@@ -390,6 +402,8 @@ def run_batched(fh, synth, tune, ceilings, dev, stream, K, W, check_oracle, plai
         s_b = ms_b * 1e-3
         work_b = {"in_grid_pairs": pairs_b, "in_grid_fraction": round(pairs_b / Ub, 5),
                   "in_grid_pairs_per_s": pairs_b / s_b, "lds_atomic_lane_ops_per_s": 2 * pairs_b / s_b}
+        if plain:
+            work_b["in_grid_pairs_per_s_plain"] = pairs_b / (ms_p * 1e-3)
         lds_peak = 32 * 256 * 2.4e9  # LDS atomic lane-ops/s: 32 lanes/clk/CU, 256 CUs, 2.4 GHz
         work_b["lds_atomic_roof"] = {"achieved": round(2 * pairs_b / s_b / 1e12, 4), "peak": round(lds_peak / 1e12, 3),
                                      "unit": "T atomic lane-ops/s", "frac": round(2 * pairs_b / s_b / lds_peak, 4),
@@ -689,6 +703,8 @@ def main():
             lds_peak = 32 * 256 * 2.4e9 / 1e12  # 32 lanes/clk/CU, 256 CUs, 2.4 GHz
             out["in_grid_pairs_per_step"] = in_grid
             out["in_grid_pairs_per_s"] = in_grid / (ms * 1e-3)
+            out["step_unfused_serial_in_grid_pairs_per_s"] = in_grid / (ms_serial * 1e-3)
+            out["hough_only_in_grid_pairs_per_s"] = in_grid / (ms_hough * 1e-3)
             out["work"] = {"in_grid_pairs": in_grid, "in_grid_fraction": round(in_grid / U, 5),
                            "in_grid_pairs_per_s": in_grid / s_k,
                            "fp64_roof": {"achieved": round(fp64, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
