@@ -50,14 +50,21 @@ def refine(dev, spec_like, row_ptr, bin_, cands, dx0: float, dk, over: int = 10,
                              x0_min=g.x0_min, dx0=g.dx0, n_x0=g.n_x0))
         grids_.append(g)
         maps.append(torch.empty((len(g.k), g.n_x0), dtype=torch.int32, device=dev))
+    best = []
     if plans:
         b = fh.Batch(plans, [(row_ptr, bin_)] * len(plans), maps)
         b.launch()
-        torch.cuda.synchronize()
+        # the best cell of every refined map on the GPU: the selection with one
+        # square per map (largest count; ties: smallest row, then smallest column)
+        best = b.select(1, 1, 1)
         b.destroy()
     out = []
-    for g, m in zip(grids_, maps):
-        h = m.cpu().numpy()
-        r, col = np.unravel_index(int(np.argmax(h)), h.shape)
-        out.append((m, g, g.x0_min + (col + 0.5) * g.dx0, float(g.k[r]), int(h[r, col])))
+    for g, m, cl in zip(grids_, maps, best):
+        top = [c for c in cl if not c["second"]]
+        if top:
+            r, col, cnt = int(top[0]["row"]), int(top[0]["col"]), int(top[0]["count"])
+        else:  # a flat map (no spread, so no candidate): every cell ties, the first wins
+            r, col = 0, 0
+            cnt = int(m[0, 0])
+        out.append((m, g, g.x0_min + (col + 0.5) * g.dx0, float(g.k[r]), cnt))
     return out

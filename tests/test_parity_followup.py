@@ -74,7 +74,11 @@ def test_over_resolved_maps_match_oracle_and_refine(dev, oracle):
         assert (x0_min, dxf, n_x0) == (g.x0_min, g.dx0, g.n_x0) and list(ks) == list(g.k)
         d = oracle.Desc(spec.n, spec.tfft, spec.f_min, spec.f_max, spec.n_fft, ks, x0_min=x0_min, dx0=dxf,
                         n_x0=n_x0)
-        assert np.array_equal(m.cpu().numpy(), oracle.hough(d, pm.row_ptr, pm.bin))
+        ref = oracle.hough(d, pm.row_ptr, pm.bin)
+        assert np.array_equal(m.cpu().numpy(), ref)
+        # the refined cell is the oracle map's best cell (ties: smallest row, then column)
+        rr, cr = np.unravel_index(int(np.argmax(ref)), ref.shape)
+        assert (x0r, kr, cnt) == (g.x0_min + (cr + 0.5) * g.dx0, float(g.k[rr]), int(ref[rr, cr]))
     # the refined cell of the best candidate is nearer the true source than the coarse cell
     x0_true = inj.f0 ** (1.0 - spec.n)
     _, _, x0r, kr, cnt = out[0]
