@@ -702,6 +702,7 @@ def main():
             lds = 2.0 * in_grid / s_k / 1e12
             lds_peak = 32 * 256 * 2.4e9 / 1e12  # 32 lanes/clk/CU, 256 CUs, 2.4 GHz
             out["in_grid_pairs_per_step"] = in_grid
+            out["cpu_baseline"]["in_grid_pairs_per_s"] = in_grid / (dt_h + dt_s)
             out["in_grid_pairs_per_s"] = in_grid / (ms * 1e-3)
             out["step_unfused_serial_in_grid_pairs_per_s"] = in_grid / (ms_serial * 1e-3)
             out["hough_only_in_grid_pairs_per_s"] = in_grid / (ms_hough * 1e-3)
