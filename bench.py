@@ -423,6 +423,26 @@ def run_batched(fh, synth, tune, ceilings, dev, stream, K, W, check_oracle, plai
     return out
 
 
+def oracle_single_thread(n_k, n_rows=32):
+    """The oracle on one host thread (a child process with OMP_NUM_THREADS=1):
+    n_rows evenly spaced k rows of the large map, direct per-cell counting."""
+    import subprocess
+    code = ("import sys, time, json; sys.path.insert(0, %r)\n"
+            "from paper_1810_09784_amd import synth\n"
+            "from oracle import hough as oracle\n"
+            "spec = synth.cfg_single_large(); pm = synth.make_peakmap(spec)\n"
+            "rows = list(range(0, %d, %d))[:%d]\n"
+            "t = time.perf_counter(); oracle.hough(oracle.Desc.from_spec(spec), pm.row_ptr, pm.bin, rows=rows)\n"
+            "dt = time.perf_counter() - t\n"
+            "print(json.dumps({'rows': len(rows), 's': dt, 'threads': oracle.threads(), "
+            "'updates_per_s': len(rows) * pm.n_peaks / dt}))\n") % (ROOT, n_k, max(1, n_k // n_rows), n_rows)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-300:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def copy_calibration():
     """Three plain 1 GiB device copies: their FETCH_SIZE / WRITE_SIZE readings
     scale the counters of the other kernels to bytes."""
@@ -689,7 +709,8 @@ def main():
                   f"{len(rows)} of {plan.n_k} k rows (every {plan.n_k // len(rows)}th) of the same map, all "
                   f"{pm.n_peaks} peaks, direct per-cell counting, {dt_h:.2f} s wall; no selection")
         out["cpu_baseline"] = {"value": len(rows) * pm.n_peaks / (dt_h + dt_s), "unit": "updates/s",
-                               "cores": threads, "kind": "oracle", "sample": sample}
+                               "cores": threads, "kind": "oracle", "sample": sample,
+                               "single_thread": oracle_single_thread(plan.n_k)}
         out["parity_vs_oracle"] = {"checked": "whole map and candidates" if whole else f"{len(rows)} sampled rows",
                                    "equal": parity}
         if whole:
