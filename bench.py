@@ -414,12 +414,31 @@ def run_batched(fh, synth, tune, ceilings, dev, stream, K, W, check_oracle, plai
             work_b["lds_atomic_frac_measured"] = round(2 * pairs_b / s_b / l_m, 4)
             work_b["lds_atomic_roof"].update(measured_peak_random=round(l_m / 1e12, 3),
                                              frac_measured=round(2 * pairs_b / s_b / l_m, 4))
+        work_b["combined_roof"] = combined_roof(alg_b, pairs_b, s_b, ceil_b)
         out["work"] = work_b
         out["parity_vs_oracle"] = {"checked": f"all {len(specs)} maps", "equal": equal_b}
         log(f"batched: oracle on all maps in {time.perf_counter() - t:.1f} s, parity {equal_b}, "
             f"{pairs_b:.4e} in-grid pairs")
         assert equal_b, "batched GPU maps differ from the oracle"
     batch.destroy()
+    return out
+
+
+def combined_roof(alg_bytes, pairs, seconds, ceil):
+    """The kernel's time against the largest of its three lower bounds (HBM on
+    the algorithmic bytes, 2 LDS atomic lane-ops and 2 FP64 fma per in-grid
+    pair), from the data sheet and, when stored, from the measured ceilings."""
+    t = {"hbm": alg_bytes / (HBM_PEAK_GBPS * 1e9), "lds_atomic": 2.0 * pairs / (32 * 256 * 2.4e9),
+         "fp64": 4.0 * pairs / (FP64_PEAK_TFLOPS * 1e12)}
+    out = {"bound_us": {k: round(v * 1e6, 2) for k, v in t.items()}, "binding": max(t, key=t.get),
+           "frac": round(max(t.values()) / seconds, 4)}
+    if ceil:
+        c = ceil["tests"]
+        tm = {"hbm": alg_bytes / (c["hbm_read_1GiB"]["gb_per_s"] * 1e9),
+              "lds_atomic": 2.0 * pairs / (c["lds_atomic_add_random"]["g_lane_ops_per_s"] * 1e9),
+              "fp64": 4.0 * pairs / (c["fp64_fma"]["tflops"] * 1e12)}
+        out.update(bound_us_measured={k: round(v * 1e6, 2) for k, v in tm.items()},
+                   binding_measured=max(tm, key=tm.get), frac_measured=round(max(tm.values()) / seconds, 4))
     return out
 
 
@@ -741,6 +760,7 @@ def main():
                 out["work"]["fp64_roof"].update(measured_peak=f_m, frac_measured=round(fp64 / f_m, 4))
                 out["work"]["lds_atomic_roof"].update(measured_peak_random=round(l_m, 3),
                                                       frac_measured=round(lds / l_m, 4))
+            out["work"]["combined_roof"] = combined_roof(alg_bytes, in_grid, s_k, ceil)
         log(f"oracle: {len(rows)} rows in {dt_h:.2f} s + selection {dt_s:.2f} s on {threads} threads; "
             f"parity {parity}")
         assert parity, "GPU output differs from the oracle"
