@@ -6,7 +6,8 @@
 //     scatter (the pattern of the tile kernel's edge updates) and a stride of
 //     32 words (every lane on one bank);
 //   - HBM: read-only streaming, a copy, and a store;
-//   - dense BF16 matrix cores (v_mfma_f32_16x16x32_bf16, the CNN's instruction).
+//   - dense BF16 matrix cores (v_mfma_f32_16x16x32_bf16, the CNN's instruction);
+//   - VALU issue: independent 32-bit integer adds, one wave instruction each.
 // Every loop has a fixed trip count and every index is masked into its
 // buffer.  Prints one JSON object per line.
 #include <hip/hip_runtime.h>
@@ -50,6 +51,21 @@ __global__ void __launch_bounds__(256) k_fma_cvt(int* out, double b, double c) {
       a[q] = __builtin_fma(a[q], b, c);
       s ^= (int)a[q];
     }
+  out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
+// Eight independent chains of v_add_u32 per lane (written as instructions so
+// that the count is exact): the VALU issue rate with every operand ready.
+__global__ void __launch_bounds__(256) k_valu(unsigned* out, unsigned b) {
+  unsigned a[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) a[q] = threadIdx.x + q;
+  for (int i = 0; i < kIters; ++i)
+#pragma unroll
+    for (int q = 0; q < 8; ++q) asm volatile("v_add_u32 %0, %0, %1" : "+v"(a[q]) : "v"(b));
+  unsigned s = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s ^= a[q];
   out[blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
@@ -199,6 +215,10 @@ int main() {
   const double waves = (double)blocks * threads / 64;
   std::printf("{\"test\":\"mfma_bf16_16x16x32\",\"ms\":%.4f,\"tflops\":%.1f}\n", ms,
               waves * (kIters / 4) * 8 * 16384.0 / ms / 1e9);
+  ms = time_ms([&] { k_valu<<<blocks, threads>>>((unsigned*)out, 3u); }, 5);
+  const double vi = waves * kIters * 8.0 / (ms * 1e-3);  // wave instructions per second
+  std::printf("{\"test\":\"valu_issue_i32\",\"ms\":%.4f,\"g_wave_instr_per_s\":%.1f,\"per_cu_cycle_at_clock\":%.3f}\n",
+              ms, vi / 1e9, vi / (p.multiProcessorCount * (p.clockRate * 1e3)));
   CK(hipDeviceSynchronize());
   CK(hipFree(a));
   CK(hipFree(b));

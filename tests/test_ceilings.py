@@ -16,6 +16,9 @@ TESTS = {
     "hbm_copy_1GiB": ("gb_per_s", 8000.0),
     "hbm_store_1GiB": ("gb_per_s", 8000.0),
     "mfma_bf16_16x16x32": ("tflops", 2500.0),
+    # 32-bit integer adds issue faster than one wave instruction per CU cycle
+    # (measured about 1.7 at the nominal clock); two per cycle bounds them
+    "valu_issue_i32": ("g_wave_instr_per_s", 2 * 256 * 2.4),
 }
 
 
