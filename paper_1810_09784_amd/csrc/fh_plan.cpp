@@ -120,8 +120,13 @@ static void host_fft_range(const Plan& p, double C, int c0, int c1, int* ia, int
 
 // Relative cost model: one unit per (peak, row) pair handled, about 12.5
 // peaks per 160 bins of noise peakmap (threshold 2.5), one unit per
-// (row, FFT) item of the windowed mode.
+// (row, FFT) item of the windowed mode.  In the whole-FFT mode every peak
+// read also costs about kChunkPeakCost row steps for its chunk's set-up (its
+// FFT, time, A edges and row bound): fitted to per-unit times of 2717 units
+// on a 48-map batch, where the old weight of one made the tiles holding row
+// k = 0 of long maps (every FFT read, few rows each) 2-3x underestimated.
 static constexpr double kPeakDensity = 0.08;
+static constexpr double kChunkPeakCost = 4.0;
 
 static void build_profiles(Plan& p) {
   const int tx = (p.n_x0 + p.tile.cols - 1) / p.tile.cols;
@@ -159,7 +164,7 @@ static void build_profiles(Plan& p) {
           if (p.tile.mode == kModeWhole) {
             int act = 0;
             for (int r = 0; r < nrows; ++r) act += (ia[r] <= i && i < ib[r]);
-            c = kPeakDensity * p.n_f * (act + 1);
+            c = kPeakDensity * p.n_f * (act + kChunkPeakCost);
           } else {
             for (int r = 0; r < nrows; ++r) {
               if (!(ia[r] <= i && i < ib[r])) continue;
