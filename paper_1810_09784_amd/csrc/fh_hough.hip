@@ -215,7 +215,7 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Per-wave LDS scratch of the whole-FFT mode: one block of 64 FFTs.
+// Per-wave LDS scratch of the whole-FFT mode: one block of up to 64 FFTs.
 struct WaveScratch {
   double T[kWave];     // time of each FFT of the block
   int rb[kWave];       // rows that can reach the tile at that FFT
@@ -486,18 +486,21 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
     double c_first[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) c_first[q] = Cg[q];
-    // waves claim blocks of 64 FFTs in order until the range is done, so that
+    // waves claim blocks of FFTs in order until the range is done, so that
     // no wave idles while another still has several blocks to go; a wave claims
     // its next block, and loads that block's CSR offsets, while it works on the
     // current one (lane l < nb: start of FFT f0 + l; lanes >= nb: the block's end)
     int* claim = X.flags + 3;
     int f0_next = 0, rp_next = 0, rpe_next = 0;
+    // blocks of up to 64 FFTs, fewer when the unit's range is short, so that
+    // every wave of the work-group gets about two blocks
+    const int BS = uniform(max(8, min(kWave, (i_end - i_start + 2 * NW - 1) / (2 * NW))));
     auto claim_block = [&]() {
       int bi = 0;
       if (lane == 0) bi = atomicAdd(claim, 1);
-      f0_next = i_start + kWave * uniform(__builtin_amdgcn_readlane(bi, 0));
+      f0_next = i_start + BS * uniform(__builtin_amdgcn_readlane(bi, 0));
       if (f0_next < i_end) {
-        const int nbn = min(kWave, i_end - f0_next);
+        const int nbn = min(BS, i_end - f0_next);
         rp_next = G.row_ptr[f0_next + min(lane, nbn)];
         rpe_next = G.row_ptr[f0_next + nbn];
       }
@@ -506,7 +509,7 @@ __device__ __forceinline__ void tile_pairs(const MapArgs& M, const GMap& G, cons
     for (;;) {
       const int f0 = f0_next;
       if (f0 >= i_end) break;
-      const int nb = min(kWave, i_end - f0);
+      const int nb = min(BS, i_end - f0);
       const int fi = f0 + min(lane, nb - 1);
       const int rp_l = min(max(rp_next, 0), M.n_peaks);
       const int rp_e = uniform(min(max(rpe_next, 0), M.n_peaks));
