@@ -258,9 +258,10 @@ constexpr int conv_lds() {
 // Weight gradient of a 3x3 convolution on the matrix cores: dW[co][k] +=
 // sum over pixels of dY[p][co] * in_col[p][k].  Grid (tile, dx): a
 // work-group takes one tile and the three taps of one column offset dx.  Per
-// output row it stages dY transposed ([co][x]) and the input rows y-1..y+1
-// shifted by dx and transposed ([dy][ci][x], zero outside the tile), so that
-// every fragment is one aligned LDS read; the partial sums are added into dW
+// output row it uses dY transposed ([co][x]) and the input rows y-1..y+1
+// shifted by dx and transposed (three [ci][x] slots of a ring, zero outside
+// the tile; one new row per output row), so that every fragment is one
+// aligned LDS read; the partial sums are added into dW
 // (and, for dx = 0, dbias) with atomics at the end.  Each wavefront owns a
 // quarter of the work-group's K tiles for every output-channel tile, so each
 // fragment it loads feeds several MFMAs.  The transposed rows are 128 bytes
@@ -275,7 +276,7 @@ __device__ __forceinline__ int tidx(int r, int x) {  // element (r, x) of a tran
 template <int CIN, int COUT>
 __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ in, const bf16_t* __restrict__ dy,
                                                     float* __restrict__ dw, float* __restrict__ db) {
-  static_assert(CIN % 8 == 0 && COUT % 8 == 0 && HW == 64, "16-byte staging of 8 channels, 128-byte rows");
+  static_assert(CIN % 16 == 0 && COUT % 8 == 0 && HW == 64, "16-byte staging of 8 channels, 128-byte rows, K tiles within a tap");
   constexpr int K = 9 * CIN;      // columns of dW
   constexpr int KX = 3 * CIN;     // this work-group's columns: taps (0, dx), (1, dx), (2, dx)
   constexpr int MT = COUT / 16, NT = KX / 16;
@@ -295,50 +296,91 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
 #pragma unroll
     for (int j = 0; j < NTW; ++j) acc[mt][j] = f4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.f;  // dbias partial (dx = 0): threads 4 co .. 4 co + 3 hold channel co, 16 pixels each
-  for (int y = 0; y < HW; ++y) {
-    __syncthreads();
-    // dY row y transposed.  A thread takes two adjacent pixels x, x+1 (x even)
-    // and 8 channels: two 16-byte loads, 8 stores of the (x, x+1) pair as one
-    // aligned 32-bit word.
-    for (int e = tid; e < (HW / 2) * (COUT / 8); e += 256) {
-      const int x = (e / (COUT / 8)) * 2, c8 = (e % (COUT / 8)) * 8;
-      const uint4 v0 = *reinterpret_cast<const uint4*>(dyb + ((size_t)y * HW + x) * COUT + c8);
-      const uint4 v1 = *reinterpret_cast<const uint4*>(dyb + ((size_t)y * HW + x + 1) * COUT + c8);
-      const unsigned a[4] = {v0.x, v0.y, v0.z, v0.w}, b[4] = {v1.x, v1.y, v1.z, v1.w};
+  // Input rows live in a ring of three slots (row yy in slot (yy + 3) % 3), so
+  // each step stages one new input row and the dY row; both are loaded into
+  // registers while the previous row's MFMAs run.  A thread takes two adjacent
+  // pixels (or columns) x, x+1 (x even) and 8 channels: two 16-byte loads, the
+  // pair of every channel stored as one aligned 32-bit word.
+  constexpr int ND = (HW / 2) * (COUT / 8), NX = (HW / 2) * (CIN / 8);
+  constexpr int PD = (ND + 255) / 256, PX = (NX + 255) / 256;
+  uint4 rd[PD][2], rx[PX][2];
+  auto load_dy = [&](int y) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        *reinterpret_cast<unsigned*>(dyT + tidx(c8 + 2 * i, x)) = (a[i] & 0xffffu) | (b[i] << 16);
-        *reinterpret_cast<unsigned*>(dyT + tidx(c8 + 2 * i + 1, x)) = (a[i] >> 16) | (b[i] & 0xffff0000u);
+    for (int p = 0; p < PD; ++p) {
+      const int e = tid + 256 * p;
+      rd[p][0] = rd[p][1] = uint4{0u, 0u, 0u, 0u};
+      if (e < ND) {
+        const int x = (e / (COUT / 8)) * 2, c8 = (e % (COUT / 8)) * 8;
+        rd[p][0] = *reinterpret_cast<const uint4*>(dyb + ((size_t)y * HW + x) * COUT + c8);
+        rd[p][1] = *reinterpret_cast<const uint4*>(dyb + ((size_t)y * HW + x + 1) * COUT + c8);
       }
     }
-    // input rows y-1 .. y+1 shifted by dx and transposed: column x holds
-    // X[yy][x + dx - 1] (zero outside the tile).  A thread takes a column pair
-    // (x, x+1), x even, and 8 channels: two 16-byte loads, the pair of every
-    // channel stored as one aligned 32-bit word.
-    for (int e = tid; e < 3 * (HW / 2) * (CIN / 8); e += 256) {
-      const int c8 = (e % (CIN / 8)) * 8, x = ((e / (CIN / 8)) % (HW / 2)) * 2, ddy = e / ((CIN / 8) * (HW / 2));
-      const int yy = y + ddy - 1;
-      unsigned px[2][4];
+  };
+  auto store_dy = [&]() {
+#pragma unroll
+    for (int p = 0; p < PD; ++p) {
+      const int e = tid + 256 * p;
+      if (e < ND) {
+        const int x = (e / (COUT / 8)) * 2, c8 = (e % (COUT / 8)) * 8;
+        const unsigned a[4] = {rd[p][0].x, rd[p][0].y, rd[p][0].z, rd[p][0].w};
+        const unsigned c[4] = {rd[p][1].x, rd[p][1].y, rd[p][1].z, rd[p][1].w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          *reinterpret_cast<unsigned*>(dyT + tidx(c8 + 2 * i, x)) = (a[i] & 0xffffu) | (c[i] << 16);
+          *reinterpret_cast<unsigned*>(dyT + tidx(c8 + 2 * i + 1, x)) = (a[i] >> 16) | (c[i] & 0xffff0000u);
+        }
+      }
+    }
+  };
+  // input row yy shifted by dx: column x holds X[yy][x + dx - 1] (zero outside the tile)
+  auto load_x = [&](int yy) {
+#pragma unroll
+    for (int p = 0; p < PX; ++p) {
+      const int e = tid + 256 * p;
+      const int c8 = (e % (CIN / 8)) * 8, x = (e / (CIN / 8)) * 2;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int xx = x + ddx - 1 + q;
-        uint4 v = uint4{0u, 0u, 0u, 0u};
-        if (yy >= 0 && yy < HW && xx >= 0 && xx < HW)
-          v = *reinterpret_cast<const uint4*>(inb + ((size_t)yy * HW + xx) * CIN + c8);
-        px[q][0] = v.x;
-        px[q][1] = v.y;
-        px[q][2] = v.z;
-        px[q][3] = v.w;
-      }
-      const int r0 = ddy * CIN + c8;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const unsigned lo = px[0][i], hi = px[1][i];  // pixels x + dx - 1 and x + dx
-        *reinterpret_cast<unsigned*>(xT + tidx(r0 + 2 * i, x)) = (lo & 0xffffu) | (hi << 16);
-        *reinterpret_cast<unsigned*>(xT + tidx(r0 + 2 * i + 1, x)) = (lo >> 16) | (hi & 0xffff0000u);
+        rx[p][q] = uint4{0u, 0u, 0u, 0u};
+        if (e < NX && yy >= 0 && yy < HW && xx >= 0 && xx < HW)
+          rx[p][q] = *reinterpret_cast<const uint4*>(inb + ((size_t)yy * HW + xx) * CIN + c8);
       }
     }
+  };
+  auto store_x = [&](int yy) {
+    const int slot = (yy + 3) % 3;
+#pragma unroll
+    for (int p = 0; p < PX; ++p) {
+      const int e = tid + 256 * p;
+      if (e < NX) {
+        const int c8 = (e % (CIN / 8)) * 8, x = (e / (CIN / 8)) * 2;
+        const int r0 = slot * CIN + c8;
+        const unsigned lo4[4] = {rx[p][0].x, rx[p][0].y, rx[p][0].z, rx[p][0].w};
+        const unsigned hi4[4] = {rx[p][1].x, rx[p][1].y, rx[p][1].z, rx[p][1].w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const unsigned lo = lo4[i], hi = hi4[i];  // pixels x + dx - 1 and x + dx
+          *reinterpret_cast<unsigned*>(xT + tidx(r0 + 2 * i, x)) = (lo & 0xffffu) | (hi << 16);
+          *reinterpret_cast<unsigned*>(xT + tidx(r0 + 2 * i + 1, x)) = (lo >> 16) | (hi & 0xffff0000u);
+        }
+      }
+    }
+  };
+  load_x(-1);
+  store_x(-1);
+  load_x(0);
+  store_x(0);
+  load_dy(0);
+  load_x(1);
+  for (int y = 0; y < HW; ++y) {
+    __syncthreads();  // the previous row's MFMAs are done with dyT and with the slot reused now
+    store_dy();
+    store_x(y + 1);
     __syncthreads();
+    if (y + 1 < HW) {
+      load_dy(y + 1);
+      load_x(y + 2);
+    }
     if (ddx == 0 && tid < 4 * COUT) {
       const int co = tid >> 2;
 #pragma unroll
@@ -358,7 +400,9 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
       for (int j = 0; j < NTW; ++j) {
         const int nt = wave * NTW + j;
         if (nt < NT) {
-          const s8 bb = *reinterpret_cast<const s8*>(xT + tidx(nt * 16 + m, x));  // row dy * CIN + ci
+          const int kx = nt * 16, ddy = kx / CIN;  // a K tile never spans two taps (CIN % 16 == 0)
+          const int row = ((y + ddy - 1 + 3) % 3) * CIN + (kx - ddy * CIN) + m;
+          const s8 bb = *reinterpret_cast<const s8*>(xT + tidx(row, x));
 #pragma unroll
           for (int mt = 0; mt < MT; ++mt) acc[mt][j] = mfma<32>(a[mt], bb, acc[mt][j]);
         }
