@@ -259,9 +259,9 @@ constexpr int conv_lds() {
 // sum over pixels of dY[p][co] * in_col[p][k].  Grid (tile, dx): a
 // work-group takes one tile and the three taps of one column offset dx.  Per
 // output row it uses dY transposed ([co][x]) and the input rows y-1..y+1
-// shifted by dx and transposed (three [ci][x] slots of a ring, zero outside
-// the tile; one new row per output row), so that every fragment is one
-// aligned LDS read; the partial sums are added into dW
+// shifted by dx and transposed (four [ci][x] slots of a ring, zero outside
+// the tile; two output rows, so two new input rows, per step), so that every
+// fragment is one aligned LDS read; the partial sums are added into dW
 // (and, for dx = 0, dbias) with atomics at the end.  Each wavefront owns a
 // quarter of the work-group's K tiles for every output-channel tile, so each
 // fragment it loads feeds several MFMAs.  The transposed rows are 128 bytes
@@ -283,8 +283,8 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
   static_assert(KX % 16 == 0, "K tiles of 16");
   constexpr int NTW = (NT + 3) / 4;  // K tiles per wavefront
   extern __shared__ __align__(16) unsigned char smem[];
-  bf16_t* dyT = reinterpret_cast<bf16_t*>(smem);  // [COUT][HW]
-  bf16_t* xT = dyT + COUT * HW;                    // [3 dy][CIN][HW]
+  bf16_t* dyT = reinterpret_cast<bf16_t*>(smem);  // [2][COUT][HW]
+  bf16_t* xT = dyT + 2 * COUT * HW;                // [4 slots][CIN][HW]
   const int b = blockIdx.x, ddx = blockIdx.y;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, m = lane & 15;
@@ -296,44 +296,45 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
 #pragma unroll
     for (int j = 0; j < NTW; ++j) acc[mt][j] = f4{0.f, 0.f, 0.f, 0.f};
   float bsum = 0.f;  // dbias partial (dx = 0): threads 4 co .. 4 co + 3 hold channel co, 16 pixels each
-  // Input rows live in a ring of three slots (row yy in slot (yy + 3) % 3), so
-  // each step stages one new input row and the dY row; both are loaded into
-  // registers while the previous row's MFMAs run.  A thread takes two adjacent
+  // Two output rows per step.  Input rows live in a ring of four slots (row yy
+  // in slot (yy + 4) % 4), so each step stages two new input rows and two dY
+  // rows, all loaded into registers while the previous step's MFMAs run.  A thread takes two adjacent
   // pixels (or columns) x, x+1 (x even) and 8 channels: two 16-byte loads, the
   // pair of every channel stored as one aligned 32-bit word.
   constexpr int ND = (HW / 2) * (COUT / 8), NX = (HW / 2) * (CIN / 8);
   constexpr int PD = (ND + 255) / 256, PX = (NX + 255) / 256;
-  uint4 rd[PD][2], rx[PX][2];
-  auto load_dy = [&](int y) {
+  uint4 rd[2][PD][2], rx[2][PX][2];
+  auto load_dy = [&](int y, int h) {
 #pragma unroll
     for (int p = 0; p < PD; ++p) {
       const int e = tid + 256 * p;
-      rd[p][0] = rd[p][1] = uint4{0u, 0u, 0u, 0u};
-      if (e < ND) {
+      rd[h][p][0] = rd[h][p][1] = uint4{0u, 0u, 0u, 0u};
+      if (e < ND && y < HW) {
         const int x = (e / (COUT / 8)) * 2, c8 = (e % (COUT / 8)) * 8;
-        rd[p][0] = *reinterpret_cast<const uint4*>(dyb + ((size_t)y * HW + x) * COUT + c8);
-        rd[p][1] = *reinterpret_cast<const uint4*>(dyb + ((size_t)y * HW + x + 1) * COUT + c8);
+        rd[h][p][0] = *reinterpret_cast<const uint4*>(dyb + ((size_t)y * HW + x) * COUT + c8);
+        rd[h][p][1] = *reinterpret_cast<const uint4*>(dyb + ((size_t)y * HW + x + 1) * COUT + c8);
       }
     }
   };
-  auto store_dy = [&]() {
+  auto store_dy = [&](int h) {
+    bf16_t* dT = dyT + h * COUT * HW;
 #pragma unroll
     for (int p = 0; p < PD; ++p) {
       const int e = tid + 256 * p;
       if (e < ND) {
         const int x = (e / (COUT / 8)) * 2, c8 = (e % (COUT / 8)) * 8;
-        const unsigned a[4] = {rd[p][0].x, rd[p][0].y, rd[p][0].z, rd[p][0].w};
-        const unsigned c[4] = {rd[p][1].x, rd[p][1].y, rd[p][1].z, rd[p][1].w};
+        const unsigned a[4] = {rd[h][p][0].x, rd[h][p][0].y, rd[h][p][0].z, rd[h][p][0].w};
+        const unsigned c[4] = {rd[h][p][1].x, rd[h][p][1].y, rd[h][p][1].z, rd[h][p][1].w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          *reinterpret_cast<unsigned*>(dyT + tidx(c8 + 2 * i, x)) = (a[i] & 0xffffu) | (c[i] << 16);
-          *reinterpret_cast<unsigned*>(dyT + tidx(c8 + 2 * i + 1, x)) = (a[i] >> 16) | (c[i] & 0xffff0000u);
+          *reinterpret_cast<unsigned*>(dT + tidx(c8 + 2 * i, x)) = (a[i] & 0xffffu) | (c[i] << 16);
+          *reinterpret_cast<unsigned*>(dT + tidx(c8 + 2 * i + 1, x)) = (a[i] >> 16) | (c[i] & 0xffff0000u);
         }
       }
     }
   };
   // input row yy shifted by dx: column x holds X[yy][x + dx - 1] (zero outside the tile)
-  auto load_x = [&](int yy) {
+  auto load_x = [&](int yy, int h) {
 #pragma unroll
     for (int p = 0; p < PX; ++p) {
       const int e = tid + 256 * p;
@@ -341,22 +342,22 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         const int xx = x + ddx - 1 + q;
-        rx[p][q] = uint4{0u, 0u, 0u, 0u};
+        rx[h][p][q] = uint4{0u, 0u, 0u, 0u};
         if (e < NX && yy >= 0 && yy < HW && xx >= 0 && xx < HW)
-          rx[p][q] = *reinterpret_cast<const uint4*>(inb + ((size_t)yy * HW + xx) * CIN + c8);
+          rx[h][p][q] = *reinterpret_cast<const uint4*>(inb + ((size_t)yy * HW + xx) * CIN + c8);
       }
     }
   };
-  auto store_x = [&](int yy) {
-    const int slot = (yy + 3) % 3;
+  auto store_x = [&](int yy, int h) {
+    const int slot = (yy + 4) % 4;
 #pragma unroll
     for (int p = 0; p < PX; ++p) {
       const int e = tid + 256 * p;
       if (e < NX) {
         const int c8 = (e % (CIN / 8)) * 8, x = (e / (CIN / 8)) * 2;
         const int r0 = slot * CIN + c8;
-        const unsigned lo4[4] = {rx[p][0].x, rx[p][0].y, rx[p][0].z, rx[p][0].w};
-        const unsigned hi4[4] = {rx[p][1].x, rx[p][1].y, rx[p][1].z, rx[p][1].w};
+        const unsigned lo4[4] = {rx[h][p][0].x, rx[h][p][0].y, rx[h][p][0].z, rx[h][p][0].w};
+        const unsigned hi4[4] = {rx[h][p][1].x, rx[h][p][1].y, rx[h][p][1].z, rx[h][p][1].w};
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const unsigned lo = lo4[i], hi = hi4[i];  // pixels x + dx - 1 and x + dx
@@ -366,45 +367,56 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
       }
     }
   };
-  load_x(-1);
-  store_x(-1);
-  load_x(0);
-  store_x(0);
-  load_dy(0);
-  load_x(1);
-  for (int y = 0; y < HW; ++y) {
-    __syncthreads();  // the previous row's MFMAs are done with dyT and with the slot reused now
-    store_dy();
-    store_x(y + 1);
+  load_x(-1, 0);
+  store_x(-1, 0);
+  load_x(0, 0);
+  store_x(0, 0);
+  load_dy(0, 0);
+  load_dy(1, 1);
+  load_x(1, 0);
+  load_x(2, 1);
+  for (int y = 0; y < HW; y += 2) {
+    __syncthreads();  // the previous rows' MFMAs are done with dyT and with the slots reused now
+    store_dy(0);
+    store_dy(1);
+    store_x(y + 1, 0);
+    store_x(y + 2, 1);
     __syncthreads();
-    if (y + 1 < HW) {
-      load_dy(y + 1);
-      load_x(y + 2);
+    if (y + 2 < HW) {
+      load_dy(y + 2, 0);
+      load_dy(y + 3, 1);
+      load_x(y + 3, 0);
+      load_x(y + 4, 1);
     }
-    if (ddx == 0 && tid < 4 * COUT) {
-      const int co = tid >> 2;
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const uint4 v = *reinterpret_cast<const uint4*>(dyT + tidx(co, (tid & 3) * 16 + h * 8));
-        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+    for (int h = 0; h < 2; ++h) {
+      const bf16_t* dT = dyT + h * COUT * HW;
+      if (ddx == 0 && tid < 4 * COUT) {
+        const int co = tid >> 2;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) bsum += __uint_as_float(w[i] << 16) + __uint_as_float(w[i] & 0xffff0000u);
+        for (int hh = 0; hh < 2; ++hh) {
+          const uint4 v = *reinterpret_cast<const uint4*>(dT + tidx(co, (tid & 3) * 16 + hh * 8));
+          const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) bsum += __uint_as_float(w[i] << 16) + __uint_as_float(w[i] & 0xffff0000u);
+        }
       }
-    }
-    for (int pc = 0; pc < HW; pc += 32) {  // 32 pixels per MFMA step
-      const int x = pc + g * 8;
-      s8 a[MT];
+      const int yo = y + h;
+      for (int pc = 0; pc < HW; pc += 32) {  // 32 pixels per MFMA step
+        const int x = pc + g * 8;
+        s8 a[MT];
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) a[mt] = *reinterpret_cast<const s8*>(dyT + tidx(mt * 16 + m, x));
+        for (int mt = 0; mt < MT; ++mt) a[mt] = *reinterpret_cast<const s8*>(dT + tidx(mt * 16 + m, x));
 #pragma unroll
-      for (int j = 0; j < NTW; ++j) {
-        const int nt = wave * NTW + j;
-        if (nt < NT) {
-          const int kx = nt * 16, ddy = kx / CIN;  // a K tile never spans two taps (CIN % 16 == 0)
-          const int row = ((y + ddy - 1 + 3) % 3) * CIN + (kx - ddy * CIN) + m;
-          const s8 bb = *reinterpret_cast<const s8*>(xT + tidx(row, x));
+        for (int j = 0; j < NTW; ++j) {
+          const int nt = wave * NTW + j;
+          if (nt < NT) {
+            const int kx = nt * 16, ddy = kx / CIN;  // a K tile never spans two taps (CIN % 16 == 0)
+            const int row = ((yo + ddy - 1 + 4) % 4) * CIN + (kx - ddy * CIN) + m;
+            const s8 bb = *reinterpret_cast<const s8*>(xT + tidx(row, x));
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) acc[mt][j] = mfma<32>(a[mt], bb, acc[mt][j]);
+            for (int mt = 0; mt < MT; ++mt) acc[mt][j] = mfma<32>(a[mt], bb, acc[mt][j]);
+          }
         }
       }
     }
@@ -426,11 +438,6 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
     bsum += __shfl_xor(bsum, 2);
     if (tid < 4 * COUT && (tid & 3) == 0) atomicAdd(&db[tid >> 2], bsum);
   }
-}
-
-template <int CIN, int COUT>
-constexpr int wgrad_lds() {
-  return (COUT * HW + 3 * CIN * HW) * 2;
 }
 
 // ---------------------------------------------------------- conv1 (VALU) --
@@ -796,6 +803,12 @@ fh_status launch_conv(const bf16_t* in, const bf16_t* w, const float* bias, cons
   hipLaunchKernelGGL((k_conv<CIN, COUT, BWD, EPI>), dim3(B * (HW / kConvRowsPerWG)), dim3(kConvWaves * 64), lds, s,
                      in, w, bias, mask, out, rowsum);
   return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
+}
+
+// LDS of one weight-gradient work-group: two transposed dY rows and four input-row slots.
+template <int CIN, int COUT>
+constexpr int wgrad_lds() {
+  return (2 * COUT + 4 * CIN) * HW * 2;
 }
 
 template <int CIN, int COUT>
