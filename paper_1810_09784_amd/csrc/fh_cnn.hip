@@ -120,12 +120,28 @@ __device__ __forceinline__ int row_swz(int co) {
   return GW == 1 ? 0 : (co / (8 / GW)) & (GW - 1);
 }
 
-template <int CIN, int COUT, bool BWD, int EPI = 0>
+// dY of the last convolution, made from its activations where it is read:
+// the head spreads dL/dpool[c] / NPIX evenly over the pixels and the ReLU
+// passes it where the activation is positive.  a: 8 activations of one pixel,
+// g: the BF16 gradients of the same 8 channels (per tile).
+__device__ __forceinline__ uint4 head_dy(uint4 a, uint4 g) {
+  auto two = [](unsigned x, unsigned gw) {
+    const unsigned lo = __uint_as_float(x << 16) > 0.f ? (gw & 0xffffu) : 0u;
+    const unsigned hi = __uint_as_float(x & 0xffff0000u) > 0.f ? (gw & 0xffff0000u) : 0u;
+    return lo | hi;
+  };
+  return uint4{two(a.x, g.x), two(a.y, g.y), two(a.z, g.z), two(a.w, g.w)};
+}
+
+// HDY (data gradient of the last convolution): `in` holds its activations and
+// `hdy` the head's per-(tile, channel) gradient; dY is head_dy of the two.
+template <int CIN, int COUT, bool BWD, int EPI = 0, bool HDY = false>
 __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restrict__ in, const bf16_t* __restrict__ w,
                                                           const float* __restrict__ bias,
                                                           const bf16_t* __restrict__ mask, bf16_t* __restrict__ out,
-                                                          float* __restrict__ rowsum) {
+                                                          float* __restrict__ rowsum, const bf16_t* __restrict__ hdy) {
   static_assert(!BWD || EPI == 0, "row sums of the forward output only");
+  static_assert(!HDY || BWD, "dY from the head only in a data gradient");
   static_assert(CIN % 8 == 0 && (COUT * 9 * CIN) % 8 == 0 && HW % kConvRowsPerWG == 0 &&
                     kConvRowsPerWG % kConvWaves == 0, "conv layout");
   constexpr int K = 9 * CIN;
@@ -162,6 +178,10 @@ __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restri
   constexpr bool PREFETCH = !(CIN == 64 && COUT == 32);
   constexpr int SPT = PREFETCH ? (NCHUNK + NT - 1) / NT : 1;
   uint4 pre[SPT];
+  // a thread's chunks all hold the same 8 channels (NT is a multiple of VPP)
+  static_assert(NT % VPP == 0, "one channel group per thread");
+  uint4 hg = uint4{0u, 0u, 0u, 0u};
+  if constexpr (HDY) hg = reinterpret_cast<const uint4*>(hdy + (size_t)b * CIN)[tid % VPP];
   auto chunk = [&](int y0, int e) {
     const int v = e % VPP, P = e / VPP, col = P % COLS, row = P / COLS;
     const int y = y0 - 1 + row, x = col - 1;
@@ -170,8 +190,11 @@ __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restri
       val = reinterpret_cast<const uint4*>(inb + ((size_t)y * HW + x) * CIN)[v];
     return val;
   };
+  // HDY: dY is formed here, when the chunk goes to LDS, so that a prefetched
+  // load is not waited for early (head_dy of a zero chunk is zero)
   auto put = [&](int e, uint4 val) {
     const int v = e % VPP, P = e / VPP;
+    if constexpr (HDY) val = head_dy(val, hg);
     reinterpret_cast<uint4*>(xin)[P * VPP + (v ^ pix_swz<VPP>(P))] = val;
   };
   if constexpr (PREFETCH) {
@@ -273,9 +296,10 @@ __device__ __forceinline__ int tidx(int r, int x) {  // element (r, x) of a tran
   return r * HW + (((x >> 3) ^ tsw(r)) << 3) + (x & 7);
 }
 
-template <int CIN, int COUT>
+template <int CIN, int COUT, bool HDY = false>
 __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ in, const bf16_t* __restrict__ dy,
-                                                    float* __restrict__ dw, float* __restrict__ db) {
+                                                    float* __restrict__ dw, float* __restrict__ db,
+                                                    const bf16_t* __restrict__ hdy) {
   static_assert(CIN % 16 == 0 && COUT % 8 == 0 && HW == 64, "16-byte staging of 8 channels, 128-byte rows, K tiles within a tap");
   constexpr int K = 9 * CIN;      // columns of dW
   constexpr int KX = 3 * CIN;     // this work-group's columns: taps (0, dx), (1, dx), (2, dx)
@@ -304,6 +328,12 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
   constexpr int ND = (HW / 2) * (COUT / 8), NX = (HW / 2) * (CIN / 8);
   constexpr int PD = (ND + 255) / 256, PX = (NX + 255) / 256;
   uint4 rd[2][PD][2], rx[2][PX][2];
+  // HDY: `dy` holds the last convolution's activations and `hdy` the head's
+  // per-(tile, channel) gradient; a thread's dY chunks all hold the channels
+  // (tid % (COUT / 8)) * 8 .. + 8 (256 is a multiple of COUT / 8)
+  static_assert(256 % (COUT / 8) == 0, "one channel group per thread");
+  uint4 hg = uint4{0u, 0u, 0u, 0u};
+  if constexpr (HDY) hg = reinterpret_cast<const uint4*>(hdy + (size_t)b * COUT)[tid % (COUT / 8)];
   auto load_dy = [&](int y, int h) {
 #pragma unroll
     for (int p = 0; p < PD; ++p) {
@@ -322,6 +352,10 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
     for (int p = 0; p < PD; ++p) {
       const int e = tid + 256 * p;
       if (e < ND) {
+        if constexpr (HDY) {  // dY formed at the store, not at the (early) load; zero stays zero
+          rd[h][p][0] = head_dy(rd[h][p][0], hg);
+          rd[h][p][1] = head_dy(rd[h][p][1], hg);
+        }
         const int x = (e / (COUT / 8)) * 2, c8 = (e % (COUT / 8)) * 8;
         const unsigned a[4] = {rd[h][p][0].x, rd[h][p][0].y, rd[h][p][0].z, rd[h][p][0].w};
         const unsigned c[4] = {rd[h][p][1].x, rd[h][p][1].y, rd[h][p][1].z, rd[h][p][1].w};
@@ -553,55 +587,29 @@ __global__ void __launch_bounds__(C4) k_head_pool(const float* __restrict__ rows
   }
 }
 
-// Binary cross-entropy of the batch (mean) and its gradient back to act4.
-// One work-group per tile; the gradient to act4 (w5 dz / NPIX where act4 > 0)
-// goes out 8 channels (16 bytes) per thread and step.
-constexpr int kHeadBwdThreads = 1024;
-
-__global__ void __launch_bounds__(kHeadBwdThreads) k_head_bwd(const bf16_t* __restrict__ act4,
-                                                              const float* __restrict__ feat,
-                                                  const float* __restrict__ logit, const float* __restrict__ label,
-                                                  const float* __restrict__ w5, float* __restrict__ dw5,
-                                                  float* __restrict__ db5, float* __restrict__ loss,
-                                                  bf16_t* __restrict__ dact4, int B) {
-  const int b = blockIdx.x;
+// Binary cross-entropy of the batch (mean) and the head's gradients.  One
+// 64-thread work-group per tile, a thread per channel: dW5, db5 and the loss
+// by atomics, and the gradient that the pool hands to every pixel of channel
+// c, w5[c] dz / NPIX, rounded to BF16 (`hdy`).  The last convolution's
+// backward kernels read it with the activations and apply the ReLU there
+// (head_dy), so the per-pixel dY is never written out.
+static_assert(C4 == 64, "a thread per channel in one wavefront");
+__global__ void __launch_bounds__(C4) k_head_bwd(const float* __restrict__ feat, const float* __restrict__ logit,
+                                                 const float* __restrict__ label, const float* __restrict__ w5,
+                                                 float* __restrict__ dw5, float* __restrict__ db5,
+                                                 float* __restrict__ loss, bf16_t* __restrict__ hdy, int B) {
+  const int b = blockIdx.x, c = threadIdx.x;
   const float z = logit[b], yv = label[b];
   const float pr = 1.f / (1.f + expf(-z));
   const float dz = (pr - yv) / (float)B;
-  if (threadIdx.x < C4) atomicAdd(&dw5[threadIdx.x], dz * feat[b * C4 + threadIdx.x]);
-  if (threadIdx.x == 0) {
+  atomicAdd(&dw5[c], dz * feat[b * C4 + c]);
+  if (c == 0) {
     atomicAdd(db5, dz);
     // log(1 + e^-|z|) form of -[y log p + (1 - y) log(1 - p)]
     const float l = fmaxf(z, 0.f) - z * yv + log1pf(expf(-fabsf(z)));
     atomicAdd(loss, l / (float)B);
   }
-  static_assert(C4 % 8 == 0, "8 channels per 16 bytes");
-  constexpr int NV = NPIX * C4 / 8, PER = NV / kHeadBwdThreads, U = 4;  // 16-byte vectors
-  static_assert(NV % kHeadBwdThreads == 0 && PER % U == 0 && kHeadBwdThreads % (C4 / 8) == 0,
-                "a thread's vectors all hold the same 8 channels");
-  const uint4* a = reinterpret_cast<const uint4*>(act4 + (size_t)b * NPIX * C4);
-  uint4* d = reinterpret_cast<uint4*>(dact4 + (size_t)b * NPIX * C4);
-  const int c = (threadIdx.x % (C4 / 8)) * 8;
-  float gw[8];  // the gradient of each of the thread's channels where act4 > 0
-#pragma unroll
-  for (int j = 0; j < 8; ++j) gw[j] = dz * w5[c + j] * (1.0f / NPIX);
-  for (int k = 0; k < PER; k += U) {
-    uint4 v[U];  // U loads in flight
-#pragma unroll
-    for (int u = 0; u < U; ++u) v[u] = a[threadIdx.x + (k + u) * kHeadBwdThreads];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const unsigned w[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-      unsigned o[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float g0 = __uint_as_float(w[i] << 16) > 0.f ? gw[2 * i] : 0.f;
-        const float g1 = __uint_as_float(w[i] & 0xffff0000u) > 0.f ? gw[2 * i + 1] : 0.f;
-        o[i] = (unsigned)f2bf(g0) | ((unsigned)f2bf(g1) << 16);
-      }
-      d[threadIdx.x + (k + u) * kHeadBwdThreads] = uint4{o[0], o[1], o[2], o[3]};
-    }
-  }
+  hdy[b * C4 + c] = f2bf(dz * w5[c] * (1.0f / NPIX));
 }
 
 // ------------------------------------------------------------- optimiser --
@@ -761,7 +769,8 @@ struct fh_cnn_s {
   float* w1r = nullptr;  // conv1 weights rounded to BF16, then its biases
   bf16_t *w2 = nullptr, *w3 = nullptr, *w4 = nullptr, *w2t = nullptr, *w3t = nullptr, *w4t = nullptr;
   bf16_t *x = nullptr, *a1 = nullptr, *a2 = nullptr, *a3 = nullptr, *a4 = nullptr;  // activations
-  bf16_t *d1 = nullptr, *d2 = nullptr, *d3 = nullptr, *d4 = nullptr;               // activation gradients
+  bf16_t *d1 = nullptr, *d2 = nullptr, *d3 = nullptr;  // activation gradients
+  bf16_t* hdy = nullptr;  // [max_batch][C4]: the head's gradient per tile and channel
   float *feat = nullptr, *logit = nullptr, *loss = nullptr;
   float* rowsum = nullptr;  // [max_batch][64][64]: the last layer's row sums per channel
   float *row_mean = nullptr, *row_istd = nullptr;
@@ -786,22 +795,22 @@ bool dalloc(T** p, size_t n) {
 void cnn_free(fh_cnn_s* c) {
   if (!c) return;
   void* ptrs[] = {c->params, c->grads, c->m1,  c->m2,   c->w1r, c->w2,    c->w3,    c->w4, c->w2t, c->w3t, c->w4t, c->x,
-                  c->a1,     c->a2,    c->a3,  c->a4,   c->d1,    c->d2,    c->d3, c->d4,  c->feat, c->logit,
+                  c->a1,     c->a2,    c->a3,  c->a4,   c->d1,    c->d2,    c->d3, c->hdy, c->feat, c->logit,
                   c->loss,   c->row_mean, c->row_istd, c->origins, c->ptab, c->rowsum};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete c;
 }
 
-template <int CIN, int COUT, bool BWD, int EPI = 0>
+template <int CIN, int COUT, bool BWD, int EPI = 0, bool HDY = false>
 fh_status launch_conv(const bf16_t* in, const bf16_t* w, const float* bias, const bf16_t* mask, bf16_t* out, int B,
-                      hipStream_t s, float* rowsum = nullptr) {
+                      hipStream_t s, float* rowsum = nullptr, const bf16_t* hdy = nullptr) {
   constexpr int lds = conv_lds<CIN, COUT>();
-  (void)hipFuncSetAttribute((const void*)k_conv<CIN, COUT, BWD, EPI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute((const void*)k_conv<CIN, COUT, BWD, EPI, HDY>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds);
   static_assert(lds <= 160 * 1024, "conv LDS");
-  hipLaunchKernelGGL((k_conv<CIN, COUT, BWD, EPI>), dim3(B * (HW / kConvRowsPerWG)), dim3(kConvWaves * 64), lds, s,
-                     in, w, bias, mask, out, rowsum);
+  hipLaunchKernelGGL((k_conv<CIN, COUT, BWD, EPI, HDY>), dim3(B * (HW / kConvRowsPerWG)), dim3(kConvWaves * 64), lds,
+                     s, in, w, bias, mask, out, rowsum, hdy);
   return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
 }
 
@@ -811,11 +820,13 @@ constexpr int wgrad_lds() {
   return (2 * COUT + 4 * CIN) * HW * 2;
 }
 
-template <int CIN, int COUT>
-fh_status launch_wgrad(const bf16_t* in, const bf16_t* dy, float* dw, float* db, int B, hipStream_t s) {
+template <int CIN, int COUT, bool HDY = false>
+fh_status launch_wgrad(const bf16_t* in, const bf16_t* dy, float* dw, float* db, int B, hipStream_t s,
+                       const bf16_t* hdy = nullptr) {
   constexpr int lds = wgrad_lds<CIN, COUT>();
-  (void)hipFuncSetAttribute((const void*)k_conv_wgrad<CIN, COUT>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  hipLaunchKernelGGL((k_conv_wgrad<CIN, COUT>), dim3(B, 3), dim3(256), lds, s, in, dy, dw, db);
+  (void)hipFuncSetAttribute((const void*)k_conv_wgrad<CIN, COUT, HDY>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds);
+  hipLaunchKernelGGL((k_conv_wgrad<CIN, COUT, HDY>), dim3(B, 3), dim3(256), lds, s, in, dy, dw, db, hdy);
   return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
 }
 
@@ -845,7 +856,8 @@ extern "C" fh_status fh_cnn_create(int32_t max_batch, fh_cnn_t* out) {
             dalloc(&c->m2, NPARAM) && dalloc(&c->w1r, NW1 + C1) && dalloc(&c->w2, NW2) && dalloc(&c->w3, NW3) && dalloc(&c->w4, NW4) &&
             dalloc(&c->w2t, NW2) && dalloc(&c->w3t, NW3) && dalloc(&c->w4t, NW4) && dalloc(&c->x, P) &&
             dalloc(&c->a1, P * C1) && dalloc(&c->a2, P * C2) && dalloc(&c->a3, P * C3) && dalloc(&c->a4, P * C4) &&
-            dalloc(&c->d1, P * C1) && dalloc(&c->d2, P * C2) && dalloc(&c->d3, P * C3) && dalloc(&c->d4, P * C4) &&
+            dalloc(&c->d1, P * C1) && dalloc(&c->d2, P * C2) && dalloc(&c->d3, P * C3) &&
+            dalloc(&c->hdy, (size_t)max_batch * C4) &&
             dalloc(&c->feat, (size_t)max_batch * C4) && dalloc(&c->logit, max_batch) && dalloc(&c->loss, 1) &&
             dalloc(&c->rowsum, (size_t)max_batch * HW * C4) &&
             dalloc(&c->origins, max_batch);
@@ -991,10 +1003,11 @@ extern "C" fh_status fh_cnn_backward(fh_cnn_t h, const float* labels, int32_t B,
   hipStream_t s = (hipStream_t)stream;
   if (hipMemsetAsync(c->grads, 0, NPARAM * 4, s) != hipSuccess || hipMemsetAsync(c->loss, 0, 4, s) != hipSuccess)
     return FH_EDEVICE;
-  hipLaunchKernelGGL(k_head_bwd, dim3(B), dim3(kHeadBwdThreads), 0, s, c->a4, c->feat, c->logit, labels, c->params + OFF_W5,
-                     c->grads + OFF_W5, c->grads + OFF_B5, c->loss, c->d4, B);
-  fh_status st = launch_wgrad<C3, C4>(c->a3, c->d4, c->grads + OFF_W4, c->grads + OFF_B4, B, s);
-  if (st == FH_OK) st = launch_conv<C4, C3, true>(c->d4, c->w4t, nullptr, c->a3, c->d3, B, s);
+  hipLaunchKernelGGL(k_head_bwd, dim3(B), dim3(C4), 0, s, c->feat, c->logit, labels, c->params + OFF_W5,
+                     c->grads + OFF_W5, c->grads + OFF_B5, c->loss, c->hdy, B);
+  // the last convolution's dY: from its activations a4 and the head's gradient
+  fh_status st = launch_wgrad<C3, C4, true>(c->a3, c->a4, c->grads + OFF_W4, c->grads + OFF_B4, B, s, c->hdy);
+  if (st == FH_OK) st = launch_conv<C4, C3, true, 0, true>(c->a4, c->w4t, nullptr, c->a3, c->d3, B, s, nullptr, c->hdy);
   if (st == FH_OK) st = launch_wgrad<C2, C3>(c->a2, c->d3, c->grads + OFF_W3, c->grads + OFF_B3, B, s);
   if (st == FH_OK) st = launch_conv<C3, C2, true>(c->d3, c->w3t, nullptr, c->a2, c->d2, B, s);
   if (st == FH_OK) st = launch_wgrad<C1, C2>(c->a1, c->d2, c->grads + OFF_W2, c->grads + OFF_B2, B, s);
