@@ -502,18 +502,24 @@ __global__ void __launch_bounds__(256) k_conv1_fwd(const bf16_t* __restrict__ in
   for (int q = 0; q < C1 / 8; ++q) o[q] = uint4{pk[4 * q], pk[4 * q + 1], pk[4 * q + 2], pk[4 * q + 3]};
 }
 
-// dW1[co][tap] = sum_p dY1[p][co] * in[p + tap]; one work-group per tile.
+// dW1[co][tap] = sum_p dY1[p][co] * in[p + tap]; kConv1WgradParts work-groups
+// per tile, each over a run of its pixels (two: 160 accumulators and two
+// pixels' loads per thread fit two wavefronts per SIMD, so two work-groups
+// share a CU; one work-group per tile with four pixels in flight took 42
+// against 33 us per 256 tiles, four parts 47 us).
+constexpr int kConv1WgradParts = 2;
 __global__ void __launch_bounds__(256) k_conv1_wgrad(const bf16_t* __restrict__ in, const bf16_t* __restrict__ dy,
                                                      float* __restrict__ dw, float* __restrict__ db) {
-  constexpr int NA = C1 * 9 + C1, PU = 4;  // accumulators per thread; pixels whose loads are in flight together
-  static_assert(C1 == 16 && NPIX % (256 * PU) == 0, "reduction layout: 16 channels, whole pixel steps");
+  constexpr int NA = C1 * 9 + C1, PU = 2;  // accumulators per thread; pixels whose loads are in flight together
+  constexpr int NP = NPIX / kConv1WgradParts;  // pixels of one work-group
+  static_assert(C1 == 16 && NP % (256 * PU) == 0, "reduction layout: 16 channels, whole pixel steps");
   static_assert(C1 % 8 == 0, "16-byte loads of 8 channels");
   __shared__ float part[256][C1 + 1];
   __shared__ float part2[16][C1 + 1];
-  const int b = blockIdx.x, tid = threadIdx.x;
+  const int b = blockIdx.x / kConv1WgradParts, pb = (blockIdx.x % kConv1WgradParts) * NP, tid = threadIdx.x;
   float acc[NA];
   for (int e = 0; e < NA; ++e) acc[e] = 0.f;
-  for (int p0 = tid; p0 < NPIX; p0 += 256 * PU) {
+  for (int p0 = pb + tid; p0 < pb + NP; p0 += 256 * PU) {
     float v[PU][9];
     uint4 dq[PU][C1 / 8];
 #pragma unroll
@@ -1013,7 +1019,8 @@ extern "C" fh_status fh_cnn_backward(fh_cnn_t h, const float* labels, int32_t B,
   if (st == FH_OK) st = launch_wgrad<C1, C2>(c->a1, c->d2, c->grads + OFF_W2, c->grads + OFF_B2, B, s);
   if (st == FH_OK) st = launch_conv<C2, C1, true>(c->d2, c->w2t, nullptr, c->a1, c->d1, B, s);
   if (st != FH_OK) return st;
-  hipLaunchKernelGGL(k_conv1_wgrad, dim3(B), dim3(256), 0, s, c->x, c->d1, c->grads + OFF_W1, c->grads + OFF_B1);
+  hipLaunchKernelGGL(k_conv1_wgrad, dim3(B * kConv1WgradParts), dim3(256), 0, s, c->x, c->d1, c->grads + OFF_W1,
+                     c->grads + OFF_B1);
   if (loss && hipMemcpyAsync(loss, c->loss, 4, hipMemcpyDeviceToDevice, s) != hipSuccess) return FH_EDEVICE;
   return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
 }
