@@ -476,7 +476,7 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const bf16_t* __restrict__ i
 
 // ---------------------------------------------------------- conv1 (VALU) --
 // w1r: the conv1 weights already rounded to BF16 (as FP32), then the FP32
-// biases (k_round_conv1); every thread reads them at the same addresses, so
+// biases (pack_param); every thread reads them at the same addresses, so
 // they come through the scalar cache.
 __global__ void __launch_bounds__(256) k_conv1_fwd(const bf16_t* __restrict__ in, const float* __restrict__ w1r,
                                                    bf16_t* __restrict__ out, int B) {
@@ -618,9 +618,42 @@ __global__ void __launch_bounds__(C4) k_head_bwd(const float* __restrict__ feat,
   hdy[b * C4 + c] = f2bf(dz * w5[c] * (1.0f / NPIX));
 }
 
+// The copies of the parameters that the kernels read, made from the FP32
+// master values: conv1's weights rounded to BF16 (kept as FP32) followed by
+// its FP32 biases (w1r), and for conv2..conv4 the BF16 weights w ([Cout][9 Cin])
+// and their flipped transpose wt ([Cin][9 Cout], k' = ((2-dy)*3 + (2-dx))*Cout
+// + co), which the data gradient uses.  One parameter (flat index e, value v)
+// at a time, so that the optimiser's update writes them as it goes.
+struct PackDst {
+  float* w1r;
+  bf16_t *w2, *w2t, *w3, *w3t, *w4, *w4t;
+};
+
+__device__ __forceinline__ void pack_conv(int e, int cin, int cout, float v, bf16_t* w, bf16_t* wt) {
+  const int co = e / (9 * cin), k = e % (9 * cin), tap = k / cin, ci = k % cin;
+  const bf16_t h = f2bf(v);
+  w[e] = h;
+  wt[(size_t)ci * 9 * cout + (8 - tap) * cout + co] = h;
+}
+
+__device__ __forceinline__ void pack_param(const PackDst& d, int e, float v) {
+  static_assert(OFF_W1 == 0 && OFF_B1 == NW1, "conv1's biases follow its weights at the start");
+  if (e < OFF_B1) d.w1r[e] = bf2f(f2bf(v));
+  else if (e < OFF_W2) d.w1r[e] = v;
+  else if (e >= OFF_W2 && e < OFF_W2 + NW2) pack_conv(e - OFF_W2, C1, C2, v, d.w2, d.w2t);
+  else if (e >= OFF_W3 && e < OFF_W3 + NW3) pack_conv(e - OFF_W3, C2, C3, v, d.w3, d.w3t);
+  else if (e >= OFF_W4 && e < OFF_W4 + NW4) pack_conv(e - OFF_W4, C3, C4, v, d.w4, d.w4t);
+}
+
+__global__ void k_pack(const float* __restrict__ p, PackDst d) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < NPARAM) pack_param(d, e, p[e]);
+}
+
 // ------------------------------------------------------------- optimiser --
 __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
-                       float* __restrict__ m2, int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+                       float* __restrict__ m2, int n, float lr, float b1, float b2, float eps, float c1, float c2,
+                       PackDst d) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
@@ -628,27 +661,9 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
   const float v = b2 * m2[i] + (1.f - b2) * gi * gi;
   m1[i] = a;
   m2[i] = v;
-  p[i] -= lr * (a / c1) / (sqrtf(v / c2) + eps);
-}
-
-// BF16 weight copies for the matrix cores: w (forward, [Cout][9 Cin]) and the
-// flipped transpose wt ([Cin][9 Cout], k' = ((2-dy)*3 + (2-dx))*Cout + co)
-// used by the data gradient.
-__global__ void k_pack(const float* __restrict__ src, int cin, int cout, bf16_t* __restrict__ w,
-                       bf16_t* __restrict__ wt) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= cout * 9 * cin) return;
-  const int co = e / (9 * cin), k = e % (9 * cin), tap = k / cin, ci = k % cin;
-  const bf16_t h = f2bf(src[e]);
-  w[e] = h;
-  if (wt) wt[(size_t)ci * 9 * cout + (8 - tap) * cout + co] = h;
-}
-
-// conv1's weights rounded to BF16 (kept as FP32) followed by its FP32 biases.
-__global__ void k_round_conv1(const float* __restrict__ src, float* __restrict__ w1r) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < NW1) w1r[e] = bf2f(f2bf(src[e]));
-  else if (e < NW1 + C1) w1r[e] = src[e];
+  const float pi = p[i] - lr * (a / c1) / (sqrtf(v / c2) + eps);
+  p[i] = pi;
+  pack_param(d, i, pi);  // the kernels' copies of the updated parameter
 }
 
 // ---------------------------------------------------------- tile inputs --
@@ -836,17 +851,10 @@ fh_status launch_wgrad(const bf16_t* in, const bf16_t* dy, float* dw, float* db,
   return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
 }
 
+PackDst pack_dst(const fh_cnn_s* c) { return PackDst{c->w1r, c->w2, c->w2t, c->w3, c->w3t, c->w4, c->w4t}; }
+
 fh_status pack(fh_cnn_s* c, hipStream_t s) {
-  const struct {
-    int off, cin, cout;
-    bf16_t *w, *wt;
-  } L[3] = {{OFF_W2, C1, C2, c->w2, c->w2t}, {OFF_W3, C2, C3, c->w3, c->w3t}, {OFF_W4, C3, C4, c->w4, c->w4t}};
-  for (const auto& l : L) {
-    const int n = l.cout * 9 * l.cin;
-    hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, s, c->params + l.off, l.cin, l.cout, l.w, l.wt);
-  }
-  static_assert(OFF_B1 == OFF_W1 + NW1, "conv1 biases follow its weights");
-  hipLaunchKernelGGL(k_round_conv1, dim3(1), dim3(256), 0, s, c->params + OFF_W1, c->w1r);
+  hipLaunchKernelGGL(k_pack, dim3((NPARAM + 255) / 256), dim3(256), 0, s, c->params, pack_dst(c));
   return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
 }
 
@@ -1033,8 +1041,8 @@ extern "C" fh_status fh_cnn_step(fh_cnn_t h, float lr, void* stream) {
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.f - std::pow(b1, (float)c->steps), c2 = 1.f - std::pow(b2, (float)c->steps);
   hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, s, c->params, c->grads, c->m1, c->m2, NPARAM,
-                     lr, b1, b2, 1e-8f, c1, c2);
-  return pack(c, s);
+                     lr, b1, b2, 1e-8f, c1, c2, pack_dst(c));
+  return hipGetLastError() == hipSuccess ? FH_OK : FH_EDEVICE;
 }
 
 extern "C" fh_status fh_tiles(const int32_t* map, int32_t n_k, int32_t n_x0, const int32_t* origins, int32_t n_tiles,
