@@ -509,8 +509,8 @@ def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: the generalized FrequencyHough here runs on a single MI355X; "
-              "maps are independent and would shard across GPUs without any collective, which this "
-              "build does not launch. Run with --gpus 1.", file=sys.stderr)
+              "maps are independent and would shard across GPUs without any collective, which the "
+              "library does not launch. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
