@@ -172,11 +172,11 @@ __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restri
   constexpr int EL = KW / 4;  // bf16 per lane per fragment
   // A group's input rows are loaded into registers while the previous group
   // computes and written to LDS after it (SPT 16-byte chunks per thread), so
-  // staging overlaps the MFMA work.  The 64 -> 32 data gradient has no
-  // registers to spare for it (it spills) and stages in place.
+  // staging overlaps the MFMA work.  (The K loop below is unrolled by two
+  // only: fully unrolled, the 64 -> 32 data gradient needed more registers
+  // than a lane has with these chunks in flight.)
   constexpr int NCHUNK = ROWS * COLS * VPP;
-  constexpr bool PREFETCH = !(CIN == 64 && COUT == 32);
-  constexpr int SPT = PREFETCH ? (NCHUNK + NT - 1) / NT : 1;
+  constexpr int SPT = (NCHUNK + NT - 1) / NT;
   uint4 pre[SPT];
   // a thread's chunks all hold the same 8 channels (NT is a multiple of VPP)
   static_assert(NT % VPP == 0, "one channel group per thread");
@@ -197,31 +197,24 @@ __global__ void __launch_bounds__(kConvWaves * 64) k_conv(const bf16_t* __restri
     if constexpr (HDY) val = head_dy(val, hg);
     reinterpret_cast<uint4*>(xin)[P * VPP + (v ^ pix_swz<VPP>(P))] = val;
   };
-  if constexpr (PREFETCH) {
 #pragma unroll
-    for (int q = 0; q < SPT; ++q) pre[q] = chunk(yb, tid + q * NT);
-  }
+  for (int q = 0; q < SPT; ++q) pre[q] = chunk(yb, tid + q * NT);
   for (int y0 = yb; y0 < yb + kConvRowsPerWG; y0 += kConvWaves) {
     __syncthreads();  // the previous group is done with xin
-    if constexpr (PREFETCH) {
 #pragma unroll
-      for (int q = 0; q < SPT; ++q)
-        if (tid + q * NT < NCHUNK) put(tid + q * NT, pre[q]);
-    } else {
-      for (int e = tid; e < NCHUNK; e += NT) put(e, chunk(y0, e));
-    }
+    for (int q = 0; q < SPT; ++q)
+      if (tid + q * NT < NCHUNK) put(tid + q * NT, pre[q]);
     __syncthreads();
-    if constexpr (PREFETCH) {
-      if (y0 + kConvWaves < yb + kConvRowsPerWG) {
+    if (y0 + kConvWaves < yb + kConvRowsPerWG) {
 #pragma unroll
-        for (int q = 0; q < SPT; ++q) pre[q] = chunk(y0 + kConvWaves, tid + q * NT);
-      }
+      for (int q = 0; q < SPT; ++q) pre[q] = chunk(y0 + kConvWaves, tid + q * NT);
     }
     f4 acc[4][NCT];
 #pragma unroll
     for (int pt = 0; pt < 4; ++pt)
 #pragma unroll
       for (int ct = 0; ct < NCT; ++ct) acc[pt][ct] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
     for (int kc = 0; kc < K; kc += KW) {
       const int k = kc + g * EL;  // EL consecutive k inside one 16-byte chunk
       const int tap = k / CIN, ci = k % CIN;
